@@ -1,0 +1,376 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself.
+
+Each test ties one part of the oracle to a closed form, a special case that
+reduces to a library routine, an identity, brute force on a tiny grid, or the
+method's own error bound, so that a dropped term, a wrong sign or index, or a
+transposed operand fails at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle as O
+import phantoms as ph
+
+
+def tiny_geom(nx=4, nk=16, **kw):
+    o = ph.custom_optics(nx, nk, **kw)
+    return O.Geometry.of(o)
+
+
+def rand_obj(rng, nx, nk, clear_edge=True):
+    x = ph.complex_gaussian(rng, (nx, nk))
+    if clear_edge:
+        x[:, 0] = 0.0          # row m = -nz/2 has no mirror partner
+    return x
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+# ------------------------------------------------------------------ special cases of the model
+
+@pytest.mark.parametrize("nk", [16, 64])
+def test_in_focus_limit_single_ascan_is_dispersed_fft(nk):
+    """Nx = 1 (only q = 0): the Stolt map is the identity and A is a dispersed DFT per A-scan.
+
+    With k_c / dk = P an integer, exp(+i 2 k_n z_m) = exp(2 pi i (n + P - nk/2) m / nk),
+    so A eta = Re(e^{i phi} sqrt(nk) ifft(ifftshift(eta))[(n + P - nk/2) mod nk]) (numpy FFT).
+    """
+    lam = 1300e-9
+    g = O.Geometry(nx=1, nk=nk, dx=4e-6, lambda_c=lam, dlambda=lam / 7.5, waist=8e-6,
+                   z_focus=3e-4, a2=3e-10, a3=1e-16)
+    G = O.grids(g)
+    P = G.kc / G.dk
+    assert abs(P - round(P)) < 1e-6
+    P = int(round(P))
+    rng = np.random.default_rng(1)
+    eta = rand_obj(rng, 1, nk, clear_edge=False)
+    phi = O.dispersion_phase(g)
+    idx = np.mod(np.arange(nk) + P - nk // 2, nk)
+    X = math.sqrt(nk) * np.fft.ifft(np.fft.ifftshift(eta[0]))[idx]
+    want = np.real(np.exp(1j * phi) * X)
+    got = O.forward_exact(g, eta)[0]
+    assert np.abs(got - want).max() < 1e-12 * np.abs(want).max()
+    # adjoint of the same special case: place e^{-i phi} r at (n + P - nk/2) mod nk, forward FFT
+    r = rng.standard_normal((1, nk))
+    v = np.zeros(nk, np.complex128)
+    v[idx] = np.exp(-1j * phi) * r[0]
+    want_a = np.fft.fftshift(np.fft.fft(v)) / math.sqrt(nk)
+    got_a = O.adjoint_exact(g, r)[0]
+    assert np.abs(got_a - want_a).max() < 1e-12 * np.abs(want_a).max()
+
+
+def test_focal_row_object_has_no_stolt_warp():
+    """An object confined to the focal row images without defocus.
+
+    With z_f = m_f dz on the grid, c X = B e^{i phi} e^{i 2 k z_f} eta_hat[l][m_f] / sqrt(nz):
+    the kz dependence of exp(i kz z_f) and of the focal reference cancel exactly.
+    """
+    g = tiny_geom(8, 32, focus_rows=5)
+    G = O.grids(g)
+    mf = 5
+    rng = np.random.default_rng(2)
+    eta = np.zeros((g.nx, g.nk), np.complex128)
+    eta[:, mf + g.nk // 2] = ph.complex_gaussian(rng, g.nx)
+    eta_hat_row = np.fft.fft(eta[:, mf + g.nk // 2], norm="ortho")
+    B = O.beam_filter(g)
+    phi = O.dispersion_phase(g)
+    Xt = B * np.exp(1j * phi)[None, :] * np.exp(2j * G.k * mf * G.dz)[None, :] \
+        * eta_hat_row[:, None] / math.sqrt(g.nk)
+    want = np.real(np.fft.ifft(Xt, axis=0, norm="ortho"))
+    got = O.forward_exact(g, eta)
+    assert np.abs(got - want).max() < 1e-12 * np.abs(want).max()
+    # mode N agrees within its interpolation bound (relative 1e-5)
+    assert rel(O.forward_nufft(g, eta), want) < 1e-5
+
+
+@pytest.mark.parametrize("mode", ["E", "N"])
+def test_mirror_symmetry(mode):
+    """Conjugate mirror M eta[p][m] = conj(eta[p][-m]): A_{zf,a}(M eta) = A_{-zf,-a}(eta) (Eq. 6, 8).
+
+    At zero dispersion and focus the two coincide: the full-range ambiguity that the
+    dispersion encoding breaks.
+    """
+    g = tiny_geom(8, 32, focus_rows=4)
+    rng = np.random.default_rng(3)
+    eta = rand_obj(rng, g.nx, g.nk)
+    mir = np.zeros_like(eta)
+    mir[:, 1:] = np.conj(eta[:, :0:-1])
+    gm = g.with_(z_focus=-g.z_focus, a2=-g.a2, a3=-g.a3)
+    lhs = O.forward(g, mir, mode)
+    rhs = O.forward(gm, eta, mode)
+    tol = 1e-12 if mode == "E" else 2e-5
+    assert rel(lhs, rhs) < tol
+    g0 = g.with_(z_focus=0.0, a2=0.0, a3=0.0)
+    assert rel(O.forward(g0, mir, mode), O.forward(g0, eta, mode)) < tol
+    # with dispersion the mirror images differ at O(1)
+    assert rel(O.forward(g, mir, mode), O.forward(g, eta, mode)) > 0.1
+
+
+# ------------------------------------------------------------------ adjoint
+
+@pytest.mark.parametrize("mode", ["E", "N"])
+def test_adjoint_dot_product(mode):
+    """sum (A x) y = Re <x, A^H y> for the real-linear A (Eq. 12, 17)."""
+    g = tiny_geom(8, 32)
+    rng = np.random.default_rng(4)
+    x = rand_obj(rng, g.nx, g.nk, clear_edge=False)
+    y = rng.standard_normal((g.nx, g.nk))
+    Ax = O.forward(g, x, mode)
+    AHy = O.adjoint(g, y, mode)
+    lhs = np.sum(Ax * y)
+    rhs = np.real(np.vdot(x, AHy))
+    assert abs(lhs - rhs) < 1e-13 * np.linalg.norm(Ax) * np.linalg.norm(y)
+
+
+@pytest.mark.parametrize("mode", ["E", "N"])
+def test_dense_adjoint_is_transpose(mode):
+    """Brute force on a tiny grid: A^H applied to unit spectra gives the rows of the dense matrix."""
+    g = tiny_geom(4, 16)
+    M = O.dense_matrix(g, mode)
+    n = g.nx * g.nk
+    for i in range(0, n, 7):
+        e = np.zeros(n)
+        e[i] = 1.0
+        a = O.adjoint(g, e.reshape(g.nx, g.nk), mode).ravel()
+        col = np.empty(2 * n)
+        col[0::2] = a.real
+        col[1::2] = a.imag
+        assert np.abs(col - M[i]).max() < 1e-13
+
+
+# ------------------------------------------------------------------ NUFFT (mode N)
+
+def test_stolt_points_reproduce_the_phase_step():
+    """t = (omega mod 2 pi) K / 2 pi: exp(i omega) = exp(2 pi i t / K), t = g0 + J/2 + tau, tau in [0,1)."""
+    g = O.Geometry.of(ph.workload("tiny").optics)
+    G = O.grids(g)
+    kz, _ = O.axial_wavenumber(g)
+    t, g0, tau = O.stolt_points(g)
+    assert np.all((tau >= 0) & (tau < 1))
+    assert np.array_equal(g0 + g.J // 2 + tau, t)
+    assert np.abs(np.exp(1j * kz * G.dz) - np.exp(2j * math.pi * t / G.K)).max() < 1e-12
+
+
+def test_minmax_weights_match_library_least_squares():
+    """Weights of the min-max interpolator vs an SVD-based least-squares solve (LAPACK gelsd)."""
+    g = O.Geometry.of(ph.workload("tiny").optics)
+    C, m, K = O.minmax_system(g)
+    taus = np.array([0.0, 0.125, 0.37, 0.5, 0.93])
+    u = O.minmax_weights(g, taus)
+    for i, tau in enumerate(taus):
+        b = np.exp(2j * math.pi * m * (tau + g.J / 2) / K)
+        ref = scipy.linalg.lstsq(C, b, lapack_driver="gelsd")[0]
+        assert np.abs(u[i] - ref).max() < 1e-9 * np.abs(ref).max()
+
+
+def test_minmax_error_level_and_convergence_in_J():
+    """The min-max worst-case error with J = 6, 2x oversampling and KB scaling is a few 1e-6,
+    and falls by orders of magnitude at J = 8 (Fessler & Sutton 2003)."""
+    g = O.Geometry.of(ph.workload("tiny").optics)
+    taus = np.linspace(0, 1, 101)
+    e6 = O.minmax_error(g, taus)
+    assert 1e-7 < e6.max() < 1e-5
+    e8 = O.minmax_error(g.with_(J=8, kb_beta=0.0), taus)
+    assert e8.max() < e6.max() / 30
+
+
+def test_nufft_obeys_minmax_bound_against_brute_force_nudft():
+    """Per point |X_hat - X| <= E(tau) ||eta_hat column|| where X is the brute-force nonuniform DFT."""
+    g = O.Geometry.of(ph.workload("tiny").optics)
+    G = O.grids(g)
+    rng = np.random.default_rng(5)
+    eta_hat = ph.complex_gaussian(rng, (g.nx, g.nk))
+    kz, _ = O.axial_wavenumber(g)
+    t, g0, tau = O.stolt_points(g)
+    Ebound = O.minmax_error(g, tau.ravel()).reshape(tau.shape)
+    worst = 0.0
+    for l in [0, 1, g.nx // 2, g.nx - 3]:
+        X = np.exp(1j * kz[l][:, None] * G.z[None, :]) @ eta_hat[l] / math.sqrt(g.nk)
+        Y = O.isam_oracle._oversampled_spectrum(g, eta_hat[l])[0]
+        Pl = O.isam_oracle._interp_matrix(g, l)
+        Xh = Pl @ Y / math.sqrt(g.nk)
+        col = np.linalg.norm(eta_hat[l])
+        ratio = np.abs(Xh - X) / (Ebound[l] * col)
+        worst = max(worst, ratio.max())
+    assert worst <= 1.0 + 1e-6
+
+
+def test_mode_n_close_to_mode_e_on_phantom():
+    w = ph.workload("tiny")
+    g = O.Geometry.of(w.optics)
+    eta = ph.phantom(w)
+    sE = O.forward_exact(g, eta)
+    sN = O.forward_nufft(g, eta)
+    assert rel(sN, sE) < 1e-5
+    y = ph.add_noise(sE, w.snr_db, w.seed)
+    assert rel(O.adjoint_nufft(g, y), O.adjoint_exact(g, y)) < 1e-5
+
+
+def test_sampled_rows_and_columns_agree_with_full():
+    """The oracle's restricted evaluations (used for large-grid sampling) agree with the full one."""
+    g = tiny_geom(16, 64)
+    rng = np.random.default_rng(6)
+    spec = np.zeros((g.nx, g.nk), np.complex128)
+    cols = [0, 3, g.nx - 3, g.nx // 2]
+    spec[cols] = ph.complex_gaussian(rng, (len(cols), g.nk))
+    eta = np.fft.ifft(spec, axis=0, norm="ortho")
+    full = O.forward_nufft(g, eta)
+    assert rel(O.forward_nufft(g, eta, columns=cols), full) < 1e-13
+    rows = [0, 5, 31, 63]
+    assert rel(O.forward_nufft(g, eta, rows=rows), full[:, rows]) < 1e-13
+    rspec = np.zeros((g.nx, g.nk), np.complex128)
+    rspec[3] = ph.complex_gaussian(rng, g.nk)
+    rspec[g.nx - 3] = np.conj(rspec[3])
+    r = np.real(np.fft.ifft(rspec, axis=0, norm="ortho"))
+    assert rel(O.adjoint_nufft(g, r, columns=[3, g.nx - 3]), O.adjoint_nufft(g, r)) < 1e-13
+
+
+# ------------------------------------------------------------------ norm and step
+
+def test_operator_norm_from_svd_and_power_iteration():
+    """||A||^2 from the SVD of the dense realified matrix; the oracle's power iteration finds it."""
+    g = tiny_geom(4, 16)
+    M = O.dense_matrix(g, "E")
+    smax2 = scipy.linalg.svdvals(M)[0] ** 2
+    assert abs(smax2 - 1.0) < 1e-10          # unitary lateral FFT and Nz^{-1/2} depth DFT, B(0,k) = 1
+    op = O.Operator(g, "E")
+    L = O.lipschitz(op, (g.nx, g.nk), iters=200, seed=0, safety=1.0)
+    assert abs(L - smax2) < 1e-8
+    MN = O.dense_matrix(g, "N")
+    sN = scipy.linalg.svdvals(MN)[0] ** 2
+    assert abs(sN - 1.0) < 1e-4
+    # many singular values sit near 1, so the Rayleigh quotient approaches sN slowly from below
+    LN = O.lipschitz(O.Operator(g, "N"), (g.nx, g.nk), iters=200, safety=1.0)
+    assert -1e-12 <= sN - LN < 1e-5
+
+
+# ------------------------------------------------------------------ prox and FISTA
+
+def test_soft_threshold_closed_form_and_edges():
+    """Eq. 14 equals u - theta u/|u| for |u| > theta and 0 otherwise; theta = 0 is the identity."""
+    rng = np.random.default_rng(7)
+    u = ph.complex_gaussian(rng, 1000) * 3
+    theta = rng.uniform(0, 2, 1000)
+    want = np.where(np.abs(u) > theta, u - theta * u / np.abs(u), 0)
+    assert np.abs(O.soft_threshold(u, theta) - want).max() < 1e-14
+    assert O.soft_threshold(np.array([0j]), 0.5)[0] == 0
+    assert O.soft_threshold(np.array([0.5 + 0j]), 0.5)[0] == 0
+    v = np.array([1 + 2j, 0j])
+    assert np.array_equal(O.soft_threshold(v, 0.0), v)
+
+
+class DenseOp:
+    """A and A^H from a dense realified matrix (fast stand-in for tiny FISTA runs)."""
+
+    def __init__(self, M, shape):
+        self.M, self.shape = M, shape
+
+    def A(self, x):
+        v = np.empty(2 * x.size)
+        v[0::2] = x.real.ravel()
+        v[1::2] = x.imag.ravel()
+        return (self.M @ v).reshape(self.shape)
+
+    def AH(self, r):
+        v = self.M.T @ r.ravel()
+        return (v[0::2] + 1j * v[1::2]).reshape(self.shape)
+
+
+def _tiny_problem():
+    g = tiny_geom(4, 16)
+    M = O.dense_matrix(g, "E")
+    op = DenseOp(M, (g.nx, g.nk))
+    rng = np.random.default_rng(8)
+    x = np.zeros((g.nx, g.nk), np.complex128)
+    idx = rng.choice(g.nx * g.nk, 6, replace=False)
+    x.ravel()[idx] = ph.complex_gaussian(rng, 6)
+    y = op.A(x) + 0.01 * rng.standard_normal((g.nx, g.nk))
+    return g, op, y
+
+
+def test_dense_op_matches_operator():
+    g, op, y = _tiny_problem()
+    rng = np.random.default_rng(9)
+    x = rand_obj(rng, g.nx, g.nk, clear_edge=False)
+    assert rel(op.A(x), O.forward_exact(g, x)) < 1e-13
+    assert rel(op.AH(y), O.adjoint_exact(g, y)) < 1e-13
+
+
+def test_fista_zero_solution_above_lambda_max():
+    g, op, y = _tiny_problem()
+    lmax = O.lambda_max(op, y)
+    res = O.fista(op, y, lam=lmax * 1.0001, L=1.0, iters=5)
+    assert np.all(res.z == 0)
+    res = O.fista(op, y, lam=lmax * 0.9, L=1.0, iters=5)
+    assert np.any(res.z != 0)
+
+
+def test_fista_reaches_kkt_point_and_obeys_rate_bound():
+    """Optimality of the limit by the l1 KKT conditions; the O(1/k^2) rate of Beck & Teboulle 2009."""
+    g, op, y = _tiny_problem()
+    lam = 0.1 * O.lambda_max(op, y)
+    L = 1.0 + 1e-9
+    long = O.fista(op, y, lam, L, iters=20000)
+    z = long.z
+    grad = op.AH(op.A(z) - y)
+    nz = np.abs(z) > 1e-10
+    kkt_nz = np.abs(grad[nz] + lam * z[nz] / np.abs(z[nz])).max()
+    kkt_z = max(0.0, (np.abs(grad[~nz]) - lam).max()) if (~nz).any() else 0.0
+    assert kkt_nz < 1e-8 and kkt_z < 1e-8
+
+    def F(v):
+        r = op.A(v) - y
+        return 0.5 * np.sum(r * r) + lam * np.sum(np.abs(v))
+
+    Fstar = F(z)
+    short = O.fista(op, y, lam, L, iters=1)
+    for k in [1, 5, 20, 100]:
+        zk = O.fista(op, y, lam, L, iters=k).z
+        bound = 2 * L * np.sum(np.abs(z) ** 2) / (k + 1) ** 2
+        assert F(zk) - Fstar <= bound + 1e-12
+    assert short.iters == 1
+
+
+def test_fista_relative_residual_stop_and_resume():
+    g, op, y = _tiny_problem()
+    lam = 0.1 * O.lambda_max(op, y)
+    full = O.fista(op, y, lam, 1.0, iters=60)
+    a = O.fista(op, y, lam, 1.0, iters=25)
+    b = O.fista(op, y, lam, 1.0, iters=35, state=a.state)
+    assert np.array_equal(b.z, full.z)
+    stop = O.fista(op, y, lam, 1.0, iters=5000, tol=1e-3)
+    assert stop.iters < 5000 and stop.rel_res[-1] < 1e-3
+    assert all(r >= 1e-3 for r in stop.rel_res[:-1])
+
+
+def test_residual_add_back_is_one_gradient_step():
+    g, op, y = _tiny_problem()
+    lam = 0.2 * O.lambda_max(op, y)
+    plain = O.fista(op, y, lam, 1.0, iters=30)
+    added = O.fista(op, y, lam, 1.0, iters=30, add_residual=True)
+    assert rel(added.z, plain.z + op.AH(y - op.A(plain.z))) < 1e-14
+
+
+# ------------------------------------------------------------------ inputs
+
+def test_phantoms_are_seeded_and_full_range():
+    w = ph.workload("tiny")
+    a, b = ph.phantom(w), ph.phantom(w)
+    assert np.array_equal(a, b)
+    nk = w.optics.nk
+    nzr = np.nonzero(a)
+    assert np.count_nonzero(a) == 40
+    assert np.all(nzr[1] != 0) and np.all(nzr[1] != nk // 2)
+    assert np.sum(nzr[1] < nk // 2) == 20
+    wb = ph.workload("bscan")
+    o = wb.optics
+    G = O.grids(O.Geometry.of(o))
+    assert abs(o.z_focus / G.dz - 512) < 1e-9
+    edge = G.band / 2
+    assert abs(o.a2 * edge ** 2 - 40 * math.pi) < 1e-9
+    assert abs(o.a3 * edge ** 3 - 8 * math.pi) < 1e-9
