@@ -1,0 +1,153 @@
+/*
+ * isam.h -- C ABI of the MI355X full-range ISAM operator and its FISTA solve.
+ *
+ * Model (arXiv 1905.06058, Mason, Davies & Bagnaninchi):
+ *   real spectra   s = Re(K^ eta)                         (Eq. 5, 8)
+ *   operator       K^ = diag(e^{j phi}) K                 (Eq. 13)
+ *                  K  = F_<->^{-1} diag(b) N F_<->         (Eq. 16)
+ *   back-projection K^H s = N'(F_<->(s))                   (Eq. 17)
+ *   MBIR problem   argmin 1/2 ||Re(K^ eta) - s_d||^2 + lambda w^T |eta|   (Eq. 12)
+ *   solver         FISTA with the weighted complex soft threshold          (Alg. 1, Eq. 14, 15)
+ *
+ * F_<-> is the unitary lateral DFT (exp(-2 pi i l p / nx) / sqrt(nx)).  N is the
+ * Stolt resampling of Eq. 3: for lateral frequency q_l and wavenumber k_n it
+ * evaluates the object's depth spectrum at kz = sqrt(4 k_n^2 - q_l^2),
+ *   X[l][n] = nz^{-1/2} sum_m eta_hat[l][m] exp(+i kz z_m),
+ * through a min-max NUFFT (Kaiser-Bessel scaling, 2x oversampled FFT, J = 6
+ * interpolation taps).  b and the focus are folded into the pointwise factor
+ *   c[l][n] = B(q_l) e^{j phi(k_n)} e^{j (2 k_n - kz) z_f},
+ *   B(q) = exp(-q^2 w0^2 / 8) on propagating components (q^2 < 4k^2), else 0,
+ *   phi(k) = a2 (k - k0)^2 + a3 (k - k0)^3,  k0 = 2 pi / lambda_c  (Eq. 7).
+ *
+ * Sampling: nk samples uniform in k over the band 2 pi dlambda / lambda_c^2
+ * centred on k0; the full-range depth grid has nz = nk rows of pitch
+ * pi / band, row m in [-nz/2, nz/2) stored at depth index i = m + nz/2.
+ *
+ * Layouts (all row-major, caller-owned device memory):
+ *   object eta    complex64 interleaved (re, im) float pairs, [nx][nk], depth contiguous
+ *   spectra s, y  float32 [nx][nk], k contiguous
+ *   weights w     float32 [nx][nk] (same layout as eta), or NULL for w = 1
+ *
+ * Every entry point returns ISAM_OK (0) or a negative ISAM_E* code; none aborts
+ * or throws.  Work is enqueued on the given HIP stream (a hipStream_t passed as
+ * void*, NULL = the null stream) and is asynchronous unless stated otherwise.
+ * Device pointers must stay valid until the stream has completed the work.
+ * A plan owns its tables and workspace; one plan must not be used on two
+ * streams at the same time (calls on one plan are stream-ordered).
+ */
+#ifndef ISAM_H
+#define ISAM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    ISAM_OK = 0,
+    ISAM_EINVAL = -1,        /* bad argument: null pointer, size or non-finite optics */
+    ISAM_EALIAS = -2,        /* an output aliases an input */
+    ISAM_EUNSUPPORTED = -3,  /* valid but not built: J != 6, osf != 2, non power-of-two sizes,
+                                nx > 2048, nk > 4096, ny != 1, Stolt span beyond two periods */
+    ISAM_ENOMEM = -4,        /* device allocation failed */
+    ISAM_ENODEV = -5,        /* no HIP device visible */
+    ISAM_EHIP = -6,          /* a HIP runtime call failed */
+    ISAM_ENONFINITE = -7     /* FISTA met a non-finite norm (NaN/Inf in the data or divergence) */
+};
+
+typedef struct isam_plan_s* isam_plan_t;
+
+/* Geometry of one B-scan (SI units).  Sec. "Background" fixes N = nx ny nz with
+ * nz the spectrometer length; Eq. 3 the Stolt map; Eq. 7 the dispersion. */
+typedef struct {
+    int32_t nx, ny, nk;      /* A-scans, lateral rows (must be 1), spectral samples (= depth rows) */
+    double dx, dy;           /* lateral pitch [m] (dy unused while ny = 1) */
+    double lambda_c;         /* centre wavelength [m] */
+    double dlambda;          /* bandwidth [m]; sampling is uniform in k */
+    double waist;            /* Gaussian beam waist w0 [m] of the beam filter B */
+    double z_focus;          /* focal depth from zero delay [m] (any real value) */
+    double a2, a3;           /* dispersion coefficients of Eq. 7 [rad m^2], [rad m^3]; a1 = 0 */
+    int32_t J;               /* NUFFT interpolation taps (6) */
+    int32_t osf;             /* NUFFT oversampling factor (2) */
+    double kb_beta;          /* Kaiser-Bessel scaling shape; <= 0 selects 2.34 J */
+} isam_geometry;
+
+/* Result record of isam_fista. */
+typedef struct {
+    int32_t iters_run;       /* iterations executed */
+    int32_t status;          /* 0, or ISAM_ENONFINITE */
+    double rel_res;          /* relative residual r_r of Eq. 15 at the last iteration (tol > 0 only, else -1) */
+    double resid2;           /* ||A eta^k - y||^2 at the last iteration's momentum point */
+    double l1;               /* sum_i w_i |z_i| of the returned iterate (before residual add-back) */
+    double L;                /* step constant used (1/L is the gradient step) */
+} isam_fista_info;
+
+/* Create a plan for geometry *g: validates, allocates tables and workspace, and
+ * builds the tables in FP64 on the device (Stolt constants, beam filter,
+ * dispersion and focus phases, Kaiser-Bessel scaling, the min-max weight
+ * table, FFT twiddles).  Synchronises `stream` once at the end.
+ * *out receives the plan (NULL on error).  Errors: EINVAL, EUNSUPPORTED,
+ * ENODEV, ENOMEM, EHIP. */
+int isam_plan(const isam_geometry* g, void* stream, isam_plan_t* out);
+
+/* Change the calibration (a2, a3, z_focus) of an existing plan and rebuild the
+ * tables that depend on it (Eq. 7 and the focal reference); same sizes.
+ * Stream-ordered after earlier work on `stream`; synchronises it at the end. */
+int isam_set_calibration(isam_plan_t p, double a2, double a3, double z_focus, void* stream);
+
+/* Forward operator s_out = Re(K^ eta) (Eq. 5, 13, 16).
+ * eta: device complex64 [nx][nk]; s_out: device float32 [nx][nk]; must not alias.
+ * Three kernels: lateral FFT, Stolt NUFFT per lateral-frequency pair, lateral
+ * C2R inverse FFT.  Errors: EINVAL (null), EALIAS. */
+int isam_forward(isam_plan_t p, const void* eta, float* s_out, void* stream);
+
+/* Adjoint eta_out = K^^H r (Eq. 17): the adjoint of isam_forward under the real
+ * inner product Re(u^H v).  r: device float32 [nx][nk]; eta_out: device
+ * complex64 [nx][nk]; must not alias.  The transposed interpolation is a
+ * gather (no atomics): results are bitwise repeatable. */
+int isam_adjoint(isam_plan_t p, const float* r, void* eta_out, void* stream);
+
+/* Normal operator eta_out = A^H A eta with the residual pass fused: one
+ * lateral transform pair instead of two.  Same layouts as above. */
+int isam_normal(isam_plan_t p, const void* eta, void* eta_out, void* stream);
+
+/* Step constant L >= ||A||^2 (replacing the fixed 1/N step of Alg. 1): power
+ * iteration on A^H A for `iters` steps from a start vector x0 (device
+ * complex64 [nx][nk], read only) or, if x0 is NULL, from a seeded
+ * counter-based complex Gaussian (SplitMix64 + Box-Muller).  Norms are FP64.
+ * *L_out = 1.01 * final Rayleigh quotient.  Synchronises the stream. */
+int isam_lipschitz(isam_plan_t p, int iters, uint64_t seed, const void* x0, double* L_out,
+                   void* stream);
+
+/* lambda_max = max_i |(A^H y)_i| / w_i, the smallest lambda for which eta = 0
+ * solves Eq. 12.  w may be NULL (w = 1).  Synchronises the stream. */
+int isam_lambda_max(isam_plan_t p, const float* y, const float* w, double* out, void* stream);
+
+/* MBIR full-range ISAM by FISTA (Alg. 1) with step 1/L and threshold
+ * lambda w_i / L (Eq. 14).  y: device float32 [nx][nk] measured spectra;
+ * w: NULL or device float32 [nx][nk] (> 0); eta_out: device complex64
+ * [nx][nk], receives z^k (plus (1/L) A^H(y - A z^k) if add_residual).
+ * max_iter >= 0 iterations; tol > 0 enables the relative-residual stop of
+ * Eq. 15 (one host read per iteration), tol = 0 runs exactly max_iter
+ * iterations with no host synchronisation until the end.  L <= 0 runs
+ * isam_lipschitz (50 steps, seed 0) first.  info may be NULL.  Synchronises
+ * the stream at the end.  Errors: EINVAL, EALIAS, ENONFINITE (info->status). */
+int isam_fista(isam_plan_t p, const float* y, float lambda, const float* w, int max_iter,
+               float tol, double L, int add_residual, void* eta_out, isam_fista_info* info,
+               void* stream);
+
+/* Release a plan (NULL is allowed). */
+void isam_destroy(isam_plan_t p);
+
+/* Static, never-NULL description of an ISAM_* code. */
+const char* isam_strerror(int code);
+
+/* Sizes of a plan: nx, nk and the oversampled length K (any may be NULL). */
+int isam_plan_dims(isam_plan_t p, int32_t* nx, int32_t* nk, int32_t* K);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ISAM_H */

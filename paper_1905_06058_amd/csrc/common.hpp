@@ -1,0 +1,78 @@
+// Shared device helpers for the ISAM kernels (complex float2 arithmetic, reductions).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define ISAM_DEV __device__ __forceinline__
+
+ISAM_DEV float2 c2(float x, float y) { return make_float2(x, y); }
+ISAM_DEV float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+ISAM_DEV float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+ISAM_DEV float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+ISAM_DEV float2 cmulc(float2 a, float2 b) {
+    return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+ISAM_DEV float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+ISAM_DEV float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// acc += a * b
+ISAM_DEV float2 cfma(float2 a, float2 b, float2 acc) {
+    acc.x = fmaf(a.x, b.x, acc.x);
+    acc.x = fmaf(-a.y, b.y, acc.x);
+    acc.y = fmaf(a.x, b.y, acc.y);
+    acc.y = fmaf(a.y, b.x, acc.y);
+    return acc;
+}
+// acc += conj(a) * b
+ISAM_DEV float2 cfmac(float2 a, float2 b, float2 acc) {
+    acc.x = fmaf(a.x, b.x, acc.x);
+    acc.x = fmaf(a.y, b.y, acc.x);
+    acc.y = fmaf(a.x, b.y, acc.y);
+    acc.y = fmaf(-a.y, b.x, acc.y);
+    return acc;
+}
+ISAM_DEV float cabs2(float2 a) { return a.x * a.x + a.y * a.y; }
+
+// 64-wide wavefront sum by butterfly shuffles.
+ISAM_DEV float wave_sum(float v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+ISAM_DEV float wave_max(float v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Block-wide sum of NV values per thread; thread 0 writes them to out[0..NV).
+// `scratch` must hold NV * (T / 64) floats.  Ends with a barrier.
+template <int T, int NV>
+ISAM_DEV void block_sum_store(float (&v)[NV], float* scratch, float* out) {
+    constexpr int NW = T / 64;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        float s = wave_sum(v[i]);
+        if (lane == 0) scratch[i * NW + wid] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        float s = 0.f;
+        for (int w = 0; w < NW; ++w) s += scratch[threadIdx.x * NW + w];
+        out[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+// Maps launch order to tile order so that tiles sharing cache lines land on the
+// same XCD: workgroups are dispatched round-robin over the 8 XCDs, so block b
+// runs on XCD b % 8; consecutive tiles are given to blocks of one XCD.
+ISAM_DEV int xcd_tile(int b, int nblocks) {
+    constexpr int NXCD = 8;
+    if (nblocks % NXCD) return b;
+    const int per = nblocks / NXCD;
+    return (b % NXCD) * per + b / NXCD;
+}

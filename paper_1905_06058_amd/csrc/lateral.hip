@@ -1,0 +1,410 @@
+// Lateral transforms of the ISAM operator: the unitary DFT over A-scans (F_<-> of
+// Eq. 2, 16, 17), applied to every depth row / wavenumber column.
+//
+// Data are [nx][nk] with the column (depth or k) index contiguous, so the
+// transform runs across rows at stride nk.  A workgroup owns a tile of C
+// consecutive complex columns (2C real columns for the real transforms) over all
+// nx rows: it reads C*8 contiguous bytes per row, transforms in LDS, writes back.
+// Real data use the two-for-one trick: real columns (2c, 2c+1) travel as one
+// complex lane, so a C2R/R2C pair costs what one complex transform costs.
+//
+// Kernels:
+//   k_lat_c2c    complex <-> complex, sign -1 (F_<->) or +1 (F_<->^{-1})
+//   k_lat_c2r    Hermitian half [nx/2+1][nk] -> real [nx][nk]   (Re of F^{-1}, Eq. 5)
+//   k_lat_r2c    real [nx][nk] -> Hermitian half                (F of a real residual)
+//   k_lat_resid  C2R, minus y, R2C in one pass, with ||r||^2 partials (Alg. 1 gradient input)
+//   k_lat_fista  gradient step, soft threshold (Eq. 14), momentum (Alg. 1) and the
+//                forward lateral transform of the next momentum point, with Eq. 15 norms
+#include <algorithm>
+
+#include "common.hpp"
+#include "fft.hpp"
+#include "plan.hpp"
+
+namespace isam {
+namespace {
+
+template <int N>
+struct LatCfg {
+    static constexpr int P = ilog2(N);
+    static constexpr int RO = 1 << fft_radix_log(P, 0);
+    static constexpr int C = N >= 2048 ? 4 : 8;              // complex lanes per tile
+    static constexpr int NB = N / RO * C;
+    static constexpr int T = NB < 64 ? 64 : (NB > 256 ? 256 : NB);
+    static constexpr int SPAN = N / RO;
+    // the tile, and at least room for the block-reduction scratch (4 values x 4 waves)
+    static constexpr size_t LDS = (size_t)N * C * sizeof(float2) > 256 ? (size_t)N * C * sizeof(float2) : 256;
+    using Fwd = LdsFft<N, C, T, -1>;
+    using Inv = LdsFft<N, C, T, +1>;
+    static_assert(Fwd::EPT == Inv::EPT, "layouts");
+};
+
+template <int N, int SIGN>
+__global__ __launch_bounds__(LatCfg<N>::T) void k_lat_c2c(const float2* in, float2* out, int nk,
+                                                          const float2* __restrict__ tw, float scale) {
+    using Cf = LatCfg<N>;
+    using F = LdsFft<N, Cf::C, Cf::T, SIGN>;
+    extern __shared__ float2 lds[];
+    const int m0 = xcd_tile(blockIdx.x, gridDim.x) * Cf::C;
+    float2 v[F::EPT];
+#pragma unroll
+    for (int i = 0; i < F::BPTO; ++i) {
+        int c, b;
+        if (F::outer(i, c, b)) {
+#pragma unroll
+            for (int j = 0; j < Cf::RO; ++j)
+                v[i * Cf::RO + j] = in[(size_t)(b + j * Cf::SPAN) * nk + m0 + c];
+        }
+    }
+    F::run(v, lds, tw);
+#pragma unroll
+    for (int i = 0; i < F::BPTO; ++i) {
+        int c, b;
+        if (F::outer(i, c, b)) {
+#pragma unroll
+            for (int j = 0; j < Cf::RO; ++j)
+                out[(size_t)(b + j * Cf::SPAN) * nk + m0 + c] = cscale(v[i * Cf::RO + j], scale);
+        }
+    }
+}
+
+// Two real columns (2c, 2c+1) of the C2R output as one complex lane: element x of the
+// lane is Za[x] + i Zb[x], with Z[x] = conj(Z[N - x]) above N/2.
+template <int N>
+ISAM_DEV float2 hermitian_pair(const float2* zh, int nk, int x, int col) {
+    const int row = x <= N / 2 ? x : N - x;
+    const float4 z = *reinterpret_cast<const float4*>(zh + (size_t)row * nk + col);
+    return x <= N / 2 ? c2(z.x - z.w, z.y + z.z) : c2(z.x + z.w, z.z - z.y);
+}
+
+// Split the transform F of (ra + i rb) into the half spectra of ra and rb through LDS.
+template <int N, int T, int C>
+ISAM_DEV void split_store(float2* lds, const float2 (&v)[LdsFft<N, C, T, -1>::EPT], float2* rh,
+                          int nk, int n0, float scale) {
+    using F = LdsFft<N, C, T, -1>;
+    constexpr int RO = F::RO, SPAN = F::SPAN;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < F::BPTO; ++i) {
+        int c, b;
+        if (F::outer(i, c, b)) {
+#pragma unroll
+            for (int j = 0; j < RO; ++j) lds[(b + j * SPAN) * C + c] = v[i * RO + j];
+        }
+    }
+    __syncthreads();
+    const float h = 0.5f * scale;
+    for (int o = threadIdx.x; o < (N / 2 + 1) * C; o += T) {
+        const int l = o / C, c = o % C;
+        const float2 A = lds[l * C + c];
+        const float2 B = cconj(lds[((N - l) & (N - 1)) * C + c]);
+        const float2 s = cadd(A, B), d = csub(A, B);
+        *reinterpret_cast<float4*>(rh + (size_t)l * nk + n0 + 2 * c) =
+            make_float4(s.x * h, s.y * h, d.y * h, -d.x * h);
+    }
+}
+
+template <int N>
+__global__ __launch_bounds__(LatCfg<N>::T) void k_lat_c2r(const float2* __restrict__ zh,
+                                                          float* __restrict__ s, int nk,
+                                                          const float2* __restrict__ tw, float scale) {
+    using Cf = LatCfg<N>;
+    using F = typename Cf::Inv;
+    extern __shared__ float2 lds[];
+    const int n0 = xcd_tile(blockIdx.x, gridDim.x) * 2 * Cf::C;
+    float2 v[F::EPT];
+#pragma unroll
+    for (int i = 0; i < F::BPTO; ++i) {
+        int c, b;
+        if (F::outer(i, c, b)) {
+#pragma unroll
+            for (int j = 0; j < Cf::RO; ++j)
+                v[i * Cf::RO + j] = hermitian_pair<N>(zh, nk, b + j * Cf::SPAN, n0 + 2 * c);
+        }
+    }
+    F::run(v, lds, tw);
+#pragma unroll
+    for (int i = 0; i < F::BPTO; ++i) {
+        int c, b;
+        if (F::outer(i, c, b)) {
+#pragma unroll
+            for (int j = 0; j < Cf::RO; ++j)
+                *reinterpret_cast<float2*>(s + (size_t)(b + j * Cf::SPAN) * nk + n0 + 2 * c) =
+                    cscale(v[i * Cf::RO + j], scale);
+        }
+    }
+}
+
+template <int N>
+__global__ __launch_bounds__(LatCfg<N>::T) void k_lat_r2c(const float* __restrict__ r,
+                                                          float2* __restrict__ rh, int nk,
+                                                          const float2* __restrict__ tw, float scale) {
+    using Cf = LatCfg<N>;
+    using F = typename Cf::Fwd;
+    extern __shared__ float2 lds[];
+    const int n0 = xcd_tile(blockIdx.x, gridDim.x) * 2 * Cf::C;
+    float2 v[F::EPT];
+#pragma unroll
+    for (int i = 0; i < F::BPTO; ++i) {
+        int c, b;
+        if (F::outer(i, c, b)) {
+#pragma unroll
+            for (int j = 0; j < Cf::RO; ++j)
+                v[i * Cf::RO + j] =
+                    *reinterpret_cast<const float2*>(r + (size_t)(b + j * Cf::SPAN) * nk + n0 + 2 * c);
+        }
+    }
+    F::run(v, lds, tw);
+    split_store<N, Cf::T, Cf::C>(lds, v, rh, nk, n0, scale);
+}
+
+template <int N>
+__global__ __launch_bounds__(LatCfg<N>::T) void k_lat_resid(const float2* __restrict__ zh,
+                                                            const float* __restrict__ y,
+                                                            float2* __restrict__ rh, int nk,
+                                                            const float2* __restrict__ tw, float scale,
+                                                            float* __restrict__ partials) {
+    using Cf = LatCfg<N>;
+    using FI = typename Cf::Inv;
+    using FF = typename Cf::Fwd;
+    extern __shared__ float2 lds[];
+    const int n0 = xcd_tile(blockIdx.x, gridDim.x) * 2 * Cf::C;
+    float2 v[FI::EPT];
+#pragma unroll
+    for (int i = 0; i < FI::BPTO; ++i) {
+        int c, b;
+        if (FI::outer(i, c, b)) {
+#pragma unroll
+            for (int j = 0; j < Cf::RO; ++j)
+                v[i * Cf::RO + j] = hermitian_pair<N>(zh, nk, b + j * Cf::SPAN, n0 + 2 * c);
+        }
+    }
+    FI::run(v, lds, tw);
+    float acc[1] = {0.f};
+#pragma unroll
+    for (int i = 0; i < FI::BPTO; ++i) {
+        int c, b;
+        if (FI::outer(i, c, b)) {
+#pragma unroll
+            for (int j = 0; j < Cf::RO; ++j) {
+                float2 s = cscale(v[i * Cf::RO + j], scale);
+                if (y) {
+                    const float2 yv = *reinterpret_cast<const float2*>(
+                        y + (size_t)(b + j * Cf::SPAN) * nk + n0 + 2 * c);
+                    s = csub(s, yv);
+                }
+                acc[0] += s.x * s.x + s.y * s.y;
+                v[i * Cf::RO + j] = s;
+            }
+        }
+    }
+    FF::run(v, lds, tw);
+    split_store<N, Cf::T, Cf::C>(lds, v, rh, nk, n0, scale);
+    __syncthreads();
+    block_sum_store<Cf::T, 1>(acc, reinterpret_cast<float*>(lds), partials + blockIdx.x * kRedSlots);
+}
+
+// Weighted complex soft threshold of Eq. 14 with threshold theta (theta = 0: identity).
+ISAM_DEV float2 soft_threshold(float2 u, float theta) {
+    const float mag = sqrtf(u.x * u.x + u.y * u.y);
+    const float sh = fmaxf(mag - theta, 0.f);
+    const float f = theta > 0.f ? sh / (sh + theta) : 1.f;
+    return cscale(u, f);
+}
+
+template <int N, bool NORMS>
+__global__ __launch_bounds__(LatCfg<N>::T) void k_lat_fista(float2* __restrict__ eta_hat,
+                                                            const float2* __restrict__ ghat,
+                                                            float2* __restrict__ z,
+                                                            const float* __restrict__ w, int nk,
+                                                            const float2* __restrict__ tw, float scale,
+                                                            FistaStep fs, float* __restrict__ partials) {
+    using Cf = LatCfg<N>;
+    using FI = typename Cf::Inv;
+    using FF = typename Cf::Fwd;
+    constexpr int RO = Cf::RO, SPAN = Cf::SPAN;
+    extern __shared__ float2 lds[];
+    const int m0 = xcd_tile(blockIdx.x, gridDim.x) * Cf::C;
+    float2 v[FI::EPT];
+    float2 gv[NORMS ? FI::EPT : 1];
+#pragma unroll
+    for (int i = 0; i < FI::BPTO; ++i) {
+        int c, b;
+        if (FI::outer(i, c, b)) {
+#pragma unroll
+            for (int j = 0; j < RO; ++j) {
+                const size_t off = (size_t)(b + j * SPAN) * nk + m0 + c;
+                const float2 g = cscale(ghat[off], fs.step);
+                v[i * RO + j] = csub(eta_hat[off], g);          // u_hat = eta_hat - step * g_hat
+                if constexpr (NORMS) gv[i * RO + j] = g;
+            }
+        }
+    }
+    FI::run(v, lds, tw);
+    if constexpr (NORMS) FI::run(gv, lds, tw);
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < FI::BPTO; ++i) {
+        int c, b;
+        if (FI::outer(i, c, b)) {
+#pragma unroll
+            for (int j = 0; j < RO; ++j) {
+                const size_t off = (size_t)(b + j * SPAN) * nk + m0 + c;
+                const float2 u = cscale(v[i * RO + j], scale);
+                const float wt = w ? w[off] : 1.f;
+                const float2 zn = soft_threshold(u, fs.lam * fs.step * wt);
+                const float2 zp = z[off];
+                z[off] = zn;
+                if constexpr (NORMS) {
+                    const float2 g = cscale(gv[i * RO + j], scale);
+                    const float2 d = csub(zn, cadd(u, g));      // z - eta, eta = u + g
+                    acc[0] += cabs2(d);
+                    acc[1] += cabs2(g);
+                    acc[2] += cabs2(csub(zn, u));               // z - eta + g
+                }
+                acc[3] += wt * sqrtf(cabs2(zn));
+                v[i * RO + j] = cadd(zn, cscale(csub(zn, zp), fs.beta));   // next momentum point
+            }
+        }
+    }
+    FF::run(v, lds, tw);
+#pragma unroll
+    for (int i = 0; i < FF::BPTO; ++i) {
+        int c, b;
+        if (FF::outer(i, c, b)) {
+#pragma unroll
+            for (int j = 0; j < RO; ++j)
+                eta_hat[(size_t)(b + j * SPAN) * nk + m0 + c] = cscale(v[i * RO + j], scale);
+        }
+    }
+    __syncthreads();
+    block_sum_store<Cf::T, 4>(acc, reinterpret_cast<float*>(lds), partials + blockIdx.x * kRedSlots);
+}
+
+template <typename K>
+void set_lds(K kern, size_t bytes) {
+    if (bytes > 65536) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <int N>
+hipError_t launch_c2c(const float2* in, float2* out, int nk, const float2* tw, int sign, hipStream_t s) {
+    using Cf = LatCfg<N>;
+    const float scale = 1.0f / sqrtf((float)N);
+    const dim3 grid(nk / Cf::C);
+    if (sign < 0) {
+        set_lds(k_lat_c2c<N, -1>, Cf::LDS);
+        hipLaunchKernelGGL((k_lat_c2c<N, -1>), grid, dim3(Cf::T), Cf::LDS, s, in, out, nk, tw, scale);
+    } else {
+        set_lds(k_lat_c2c<N, +1>, Cf::LDS);
+        hipLaunchKernelGGL((k_lat_c2c<N, +1>), grid, dim3(Cf::T), Cf::LDS, s, in, out, nk, tw, scale);
+    }
+    return hipGetLastError();
+}
+
+template <int N>
+hipError_t launch_c2r(const float2* zh, float* sout, int nk, const float2* tw, hipStream_t s) {
+    using Cf = LatCfg<N>;
+    set_lds(k_lat_c2r<N>, Cf::LDS);
+    hipLaunchKernelGGL(k_lat_c2r<N>, dim3(nk / (2 * Cf::C)), dim3(Cf::T), Cf::LDS, s, zh, sout, nk, tw,
+                       1.0f / sqrtf((float)N));
+    return hipGetLastError();
+}
+
+template <int N>
+hipError_t launch_r2c(const float* r, float2* rh, int nk, const float2* tw, hipStream_t s) {
+    using Cf = LatCfg<N>;
+    set_lds(k_lat_r2c<N>, Cf::LDS);
+    hipLaunchKernelGGL(k_lat_r2c<N>, dim3(nk / (2 * Cf::C)), dim3(Cf::T), Cf::LDS, s, r, rh, nk, tw,
+                       1.0f / sqrtf((float)N));
+    return hipGetLastError();
+}
+
+template <int N>
+hipError_t launch_resid(const float2* zh, const float* y, float2* rh, int nk, const float2* tw,
+                        float* partials, hipStream_t s) {
+    using Cf = LatCfg<N>;
+    set_lds(k_lat_resid<N>, Cf::LDS);
+    hipLaunchKernelGGL(k_lat_resid<N>, dim3(nk / (2 * Cf::C)), dim3(Cf::T), Cf::LDS, s, zh, y, rh, nk, tw,
+                       1.0f / sqrtf((float)N), partials);
+    return hipGetLastError();
+}
+
+template <int N>
+hipError_t launch_fista(float2* eh, const float2* gh, float2* z, const float* w, int nk, const float2* tw,
+                        FistaStep fs, float* partials, hipStream_t s) {
+    using Cf = LatCfg<N>;
+    const dim3 grid(nk / Cf::C);
+    const float scale = 1.0f / sqrtf((float)N);
+    if (fs.norms) {
+        set_lds(k_lat_fista<N, true>, Cf::LDS);
+        hipLaunchKernelGGL((k_lat_fista<N, true>), grid, dim3(Cf::T), Cf::LDS, s, eh, gh, z, w, nk, tw, scale,
+                           fs, partials);
+    } else {
+        set_lds(k_lat_fista<N, false>, Cf::LDS);
+        hipLaunchKernelGGL((k_lat_fista<N, false>), grid, dim3(Cf::T), Cf::LDS, s, eh, gh, z, w, nk, tw, scale,
+                           fs, partials);
+    }
+    return hipGetLastError();
+}
+
+template <int N>
+int blocks_of(int nk, int kind) {
+    using Cf = LatCfg<N>;
+    return kind == 0 ? nk / Cf::C : nk / (2 * Cf::C);
+}
+
+}  // namespace
+
+#define ISAM_LAT_SWITCH(N_, CALL)          \
+    switch (N_) {                          \
+        case 1: { constexpr int N = 1; CALL; } \
+        case 2: { constexpr int N = 2; CALL; } \
+        case 4: { constexpr int N = 4; CALL; } \
+        case 8: { constexpr int N = 8; CALL; } \
+        case 16: { constexpr int N = 16; CALL; } \
+        case 32: { constexpr int N = 32; CALL; } \
+        case 64: { constexpr int N = 64; CALL; } \
+        case 128: { constexpr int N = 128; CALL; } \
+        case 256: { constexpr int N = 256; CALL; } \
+        case 512: { constexpr int N = 512; CALL; } \
+        case 1024: { constexpr int N = 1024; CALL; } \
+        case 2048: { constexpr int N = 2048; CALL; } \
+        default: return hipErrorInvalidValue; \
+    }
+
+hipError_t lat_c2c(const isam_plan_s* p, const float2* in, float2* out, int sign, hipStream_t s) {
+    ISAM_LAT_SWITCH(p->nx, return launch_c2c<N>(in, out, p->nk, p->twX, sign, s));
+}
+hipError_t lat_c2r(const isam_plan_s* p, const float2* zh, float* sout, hipStream_t s) {
+    ISAM_LAT_SWITCH(p->nx, return launch_c2r<N>(zh, sout, p->nk, p->twX, s));
+}
+hipError_t lat_r2c(const isam_plan_s* p, const float* r, float2* rh, hipStream_t s) {
+    ISAM_LAT_SWITCH(p->nx, return launch_r2c<N>(r, rh, p->nk, p->twX, s));
+}
+hipError_t lat_resid(const isam_plan_s* p, const float2* zh, const float* y, float2* rh, float* partials,
+                     hipStream_t s) {
+    ISAM_LAT_SWITCH(p->nx, return launch_resid<N>(zh, y, rh, p->nk, p->twX, partials, s));
+}
+hipError_t lat_fista(const isam_plan_s* p, float2* eh, const float2* gh, float2* z, const float* w,
+                     FistaStep fs, float* partials, hipStream_t s) {
+    ISAM_LAT_SWITCH(p->nx, return launch_fista<N>(eh, gh, z, w, p->nk, p->twX, fs, partials, s));
+}
+int lat_blocks(const isam_plan_s* p, int kind) {
+    switch (p->nx) {
+        case 1: return blocks_of<1>(p->nk, kind);
+        case 2: return blocks_of<2>(p->nk, kind);
+        case 4: return blocks_of<4>(p->nk, kind);
+        case 8: return blocks_of<8>(p->nk, kind);
+        case 16: return blocks_of<16>(p->nk, kind);
+        case 32: return blocks_of<32>(p->nk, kind);
+        case 64: return blocks_of<64>(p->nk, kind);
+        case 128: return blocks_of<128>(p->nk, kind);
+        case 256: return blocks_of<256>(p->nk, kind);
+        case 512: return blocks_of<512>(p->nk, kind);
+        case 1024: return blocks_of<1024>(p->nk, kind);
+        case 2048: return blocks_of<2048>(p->nk, kind);
+        default: return 0;
+    }
+}
+
+}  // namespace isam

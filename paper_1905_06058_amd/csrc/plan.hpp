@@ -1,0 +1,93 @@
+// Internal plan state shared by the ISAM library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "isam.h"
+
+namespace isam {
+
+constexpr int kJ = 6;             // interpolation taps (the only J built)
+constexpr int kPieces = 32;       // piecewise-cubic pieces of the min-max weight table over tau in [0,1)
+constexpr int kWtabEntries = kPieces * kJ * 4;   // float2 coefficients c0..c3 per piece and tap
+constexpr int kRedSlots = 8;      // scalars per workgroup in reduction partials
+
+// Constant arguments of the per-column NUFFT kernels.
+struct NufftArgs {
+    int nx, nk, K;
+    int mi;                 // integer part of the focal row (circular shift of the depth buffer)
+    int has_frac;           // nonzero if the focal row has a fractional part
+    double mr_over_K;       // fractional focal row / K (per-point phase exp(-2 pi i m_r t / K))
+    double kc, dk;          // k_n = kc + (n - nk/2) dk
+    double cT;              // Stolt grid position t = kz * cT, cT = dz K / (2 pi)
+    const double* q2;       // [nx] q_l^2 (FP64)
+    const float* Bl;        // [nx] beam filter exp(-q^2 w0^2 / 8)
+    const float2* En;       // [nk] e^{i phi(k_n)} e^{2 i k_n z_f} / sqrt(nz)
+    const float* sm;        // [nk] Kaiser-Bessel scaling at depth index i = m + nz/2
+    const float2* wtab;     // [kPieces][kJ][4] cubic coefficients of the weights (focus-phased)
+    const float2* tw;       // [K] exp(-2 pi i e / K)
+};
+
+struct Reduce {
+    float* partials;        // [maxBlocks][kRedSlots]
+    double* sums;           // [kRedSlots] final FP64 values (device)
+    int maxBlocks;
+};
+
+}  // namespace isam
+
+struct isam_plan_s {
+    isam_geometry g;
+    int device;
+    int nx, nk, K, nh;
+    double kc, band, dk, dz, cT, beta, mf;
+    int mi;
+    double mr;
+
+    // tables (device)
+    double* q2 = nullptr;
+    float* Bl = nullptr;
+    float2* En = nullptr;
+    float* sm = nullptr;
+    float2* wtab = nullptr;
+    float2* twK = nullptr;
+    float2* twX = nullptr;
+    double* wscratch = nullptr;   // FP64 scratch of the weight-table build
+
+    // workspace (device)
+    float2* etahat = nullptr;     // [nx][nk] lateral spectrum of the operator input
+    float2* zh = nullptr;         // [nh][nk] Hermitian half of the forward spectrum
+    float2* rh = nullptr;         // [nh][nk] half spectrum of a real residual
+    float2* ghat = nullptr;       // [nx][nk] lateral spectrum of the adjoint output
+    float2* fista_hat = nullptr;  // [nx][nk] FISTA momentum point in lateral frequency
+    float2* vec = nullptr;        // [nx][nk] power-iteration vector
+    float* sbuf = nullptr;        // [nx][nk] real spectra scratch
+    isam::Reduce red;
+    double* host_sums = nullptr;  // pinned host copy of red.sums
+
+    isam::NufftArgs nufft_args() const;
+};
+
+namespace isam {
+
+// launchers (return hipError_t of the launch)
+hipError_t lat_c2c(const isam_plan_s* p, const float2* in, float2* out, int sign, hipStream_t s);
+hipError_t lat_c2r(const isam_plan_s* p, const float2* zh, float* s_out, hipStream_t st);
+hipError_t lat_r2c(const isam_plan_s* p, const float* r, float2* rh, hipStream_t st);
+// residual pass: Zh -> s = C2R(Zh) -> r = s - y (y may be null) -> Rh = R2C(r); partial ||r||^2
+hipError_t lat_resid(const isam_plan_s* p, const float2* zh, const float* y, float2* rh,
+                     float* partials, hipStream_t st);
+// FISTA update pass; see solver.hip
+struct FistaStep {
+    float step, lam, beta;
+    int norms;
+};
+hipError_t lat_fista(const isam_plan_s* p, float2* eta_hat, const float2* ghat, float2* z,
+                     const float* w, FistaStep fs, float* partials, hipStream_t st);
+int lat_blocks(const isam_plan_s* p, int kind);   // number of workgroups of a lateral pass
+
+hipError_t nufft_fwd(const isam_plan_s* p, const float2* etahat, float2* zh, hipStream_t s);
+hipError_t nufft_adj(const isam_plan_s* p, const float2* rh, float2* ghat, hipStream_t s);
+int nufft_span_ok(const isam_plan_s* p);          // host check of the Stolt span bound
+
+}  // namespace isam

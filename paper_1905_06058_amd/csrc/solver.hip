@@ -1,0 +1,296 @@
+// C entry points of the operator and of the MBIR solve (Eq. 12, Alg. 1).
+//
+// isam_forward   s = Re(K^ eta)             lateral FFT -> NUFFT pairs -> C2R
+// isam_adjoint   eta = K^^H r               R2C -> transposed NUFFT pairs -> lateral IFFT
+// isam_normal    A^H A eta                  the C2R and R2C passes fused
+// isam_fista     per iteration: NUFFT (momentum point) -> residual pass (C2R, -y, R2C)
+//                -> transposed NUFFT -> update pass (IFFT, step, soft threshold, momentum,
+//                FFT of the next momentum point).  The momentum point is kept in lateral
+//                frequency, so an iteration is four passes.
+#include <algorithm>
+#include <cmath>
+
+#include "common.hpp"
+#include "plan.hpp"
+
+using namespace isam;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// FP64 sums of the per-workgroup partials, one thread per slot (fixed order: deterministic).
+__global__ void k_finalize(const float* __restrict__ partials, int nblocks, int nslots,
+                           double* __restrict__ sums, int mode_max) {
+    const int s = threadIdx.x;
+    if (s >= nslots) return;
+    double acc = 0.0;
+    for (int b = 0; b < nblocks; ++b) {
+        const double v = partials[b * kRedSlots + s];
+        acc = mode_max ? fmax(acc, v) : acc + v;
+    }
+    sums[s] = acc;
+}
+
+// Partial sum of |x|^2 (slot 0) over a complex vector; 256 threads per block.
+__global__ __launch_bounds__(256) void k_sumsq(const float2* __restrict__ x, size_t n,
+                                               float* __restrict__ partials) {
+    __shared__ float scratch[4];
+    float acc[1] = {0.f};
+    for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+        acc[0] += cabs2(x[i]);
+    block_sum_store<256, 1>(acc, scratch, partials + blockIdx.x * kRedSlots);
+}
+
+// Partial max of |x_i| / w_i (slot 0).
+__global__ __launch_bounds__(256) void k_absmax(const float2* __restrict__ x, const float* __restrict__ w,
+                                                size_t n, float* __restrict__ partials) {
+    __shared__ float scratch[4];
+    float m = 0.f;
+    for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        float v = sqrtf(cabs2(x[i]));
+        if (w) v /= w[i];
+        m = fmaxf(m, v);
+    }
+    m = wave_max(m);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) scratch[wid] = m;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        partials[blockIdx.x * kRedSlots] = fmaxf(fmaxf(scratch[0], scratch[1]), fmaxf(scratch[2], scratch[3]));
+}
+
+// x *= 1 / sqrt(sums[slot])
+__global__ void k_scale_inv_sqrt(float2* __restrict__ x, size_t n, const double* __restrict__ sums, int slot) {
+    const float f = (float)(1.0 / sqrt(sums[slot]));
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        x[i] = cscale(x[i], f);
+}
+
+// x -= a * y
+__global__ void k_axpy(float2* __restrict__ x, const float2* __restrict__ y, float a, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        x[i] = csub(x[i], cscale(y[i], a));
+}
+
+__global__ void k_zero(float2* __restrict__ x, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        x[i] = c2(0.f, 0.f);
+}
+
+// Counter-based complex Gaussian start vector: SplitMix64 (Steele, Lea & Flood 2014)
+// on (seed, index), then the Box-Muller transform; CN(0, 1) entries.
+__device__ uint64_t splitmix64(uint64_t z) {
+    z += 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+__global__ void k_randn(float2* __restrict__ x, size_t n, uint64_t seed) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const uint64_t a = splitmix64(seed ^ (2 * i)), b = splitmix64(seed ^ (2 * i + 1));
+        const double u1 = ((a >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+        const double u2 = ((b >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+        const double r = sqrt(-log(u1));            // sqrt(-2 ln u1) / sqrt(2)
+        double sn, cs;
+        sincospi(2.0 * u2, &sn, &cs);
+        x[i] = make_float2((float)(r * cs), (float)(r * sn));
+    }
+}
+
+int grid_for(size_t n) { return (int)std::min<size_t>((n + 255) / 256, 2048); }
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+    const char *pa = (const char*)a, *pb = (const char*)b;
+    return pa < pb + nb && pb < pa + na;
+}
+
+#define HIP_OK(x)                                    \
+    do {                                             \
+        if ((x) != hipSuccess) return ISAM_EHIP;     \
+    } while (0)
+
+int sum_to_host(isam_plan_t p, const float* partials, int nblocks, int nslots, int mode_max, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, partials, nblocks, nslots, p->red.sums, mode_max);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpyAsync(p->host_sums, p->red.sums, nslots * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    return ISAM_OK;
+}
+
+int forward_impl(isam_plan_t p, const float2* eta, float* s_out, hipStream_t s) {
+    HIP_OK(lat_c2c(p, eta, p->etahat, -1, s));
+    HIP_OK(nufft_fwd(p, p->etahat, p->zh, s));
+    HIP_OK(lat_c2r(p, p->zh, s_out, s));
+    return ISAM_OK;
+}
+
+int adjoint_impl(isam_plan_t p, const float* r, float2* eta_out, hipStream_t s) {
+    HIP_OK(lat_r2c(p, r, p->rh, s));
+    HIP_OK(nufft_adj(p, p->rh, p->ghat, s));
+    HIP_OK(lat_c2c(p, p->ghat, eta_out, +1, s));
+    return ISAM_OK;
+}
+
+// out = A^H (A eta - y) (y may be null); ||A eta - y||^2 partials in red.partials slot 0.
+int normal_impl(isam_plan_t p, const float2* eta, const float* y, float2* out, hipStream_t s) {
+    HIP_OK(lat_c2c(p, eta, p->etahat, -1, s));
+    HIP_OK(nufft_fwd(p, p->etahat, p->zh, s));
+    HIP_OK(lat_resid(p, p->zh, y, p->rh, p->red.partials, s));
+    HIP_OK(nufft_adj(p, p->rh, p->ghat, s));
+    HIP_OK(lat_c2c(p, p->ghat, out, +1, s));
+    return ISAM_OK;
+}
+
+}  // namespace
+
+extern "C" int isam_forward(isam_plan_t p, const void* eta, float* s_out, void* stream) {
+    if (!p || !eta || !s_out) return ISAM_EINVAL;
+    const size_t n = (size_t)p->nx * p->nk;
+    if (overlaps(eta, n * 8, s_out, n * 4)) return ISAM_EALIAS;
+    return forward_impl(p, (const float2*)eta, s_out, (hipStream_t)stream);
+}
+
+extern "C" int isam_adjoint(isam_plan_t p, const float* r, void* eta_out, void* stream) {
+    if (!p || !r || !eta_out) return ISAM_EINVAL;
+    const size_t n = (size_t)p->nx * p->nk;
+    if (overlaps(r, n * 4, eta_out, n * 8)) return ISAM_EALIAS;
+    return adjoint_impl(p, r, (float2*)eta_out, (hipStream_t)stream);
+}
+
+extern "C" int isam_normal(isam_plan_t p, const void* eta, void* eta_out, void* stream) {
+    if (!p || !eta || !eta_out) return ISAM_EINVAL;
+    const size_t n = (size_t)p->nx * p->nk;
+    if (overlaps(eta, n * 8, eta_out, n * 8)) return ISAM_EALIAS;
+    return normal_impl(p, (const float2*)eta, nullptr, (float2*)eta_out, (hipStream_t)stream);
+}
+
+extern "C" int isam_lipschitz(isam_plan_t p, int iters, uint64_t seed, const void* x0, double* L_out,
+                              void* stream) {
+    if (!p || !L_out || iters < 1) return ISAM_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t n = (size_t)p->nx * p->nk;
+    float2* x = p->vec;
+    if (x0) {
+        HIP_OK(hipMemcpyAsync(x, x0, n * sizeof(float2), hipMemcpyDeviceToDevice, s));
+    } else {
+        hipLaunchKernelGGL(k_randn, dim3(grid_for(n)), dim3(256), 0, s, x, n, seed);
+        HIP_OK(hipGetLastError());
+    }
+    const int gb = grid_for(n);
+    const int rb = lat_blocks(p, 1);
+    // normalise the start vector into red.sums[1]
+    hipLaunchKernelGGL(k_sumsq, dim3(gb), dim3(256), 0, s, x, n, p->red.partials);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, p->red.partials, gb, 1, p->red.sums + 1, 0);
+    hipLaunchKernelGGL(k_scale_inv_sqrt, dim3(gb), dim3(256), 0, s, x, n, p->red.sums, 1);
+    HIP_OK(hipGetLastError());
+    for (int it = 0; it < iters; ++it) {
+        // ||A x||^2 (the Rayleigh quotient, ||x|| = 1) lands in sums[0]; x <- A^H A x / ||.||
+        int rc = normal_impl(p, x, nullptr, x, s);   // in-place lateral pass is safe (tile-local)
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, p->red.partials, rb, 1, p->red.sums, 0);
+        hipLaunchKernelGGL(k_sumsq, dim3(gb), dim3(256), 0, s, x, n, p->red.partials);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, p->red.partials, gb, 1, p->red.sums + 1, 0);
+        hipLaunchKernelGGL(k_scale_inv_sqrt, dim3(gb), dim3(256), 0, s, x, n, p->red.sums, 1);
+        HIP_OK(hipGetLastError());
+    }
+    HIP_OK(hipMemcpyAsync(p->host_sums, p->red.sums, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    const double ray = p->host_sums[0];
+    if (!std::isfinite(ray)) return ISAM_ENONFINITE;
+    *L_out = 1.01 * ray;
+    return ISAM_OK;
+}
+
+extern "C" int isam_lambda_max(isam_plan_t p, const float* y, const float* w, double* out, void* stream) {
+    if (!p || !y || !out) return ISAM_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t n = (size_t)p->nx * p->nk;
+    int rc = adjoint_impl(p, y, p->vec, s);
+    if (rc) return rc;
+    const int gb = grid_for(n);
+    hipLaunchKernelGGL(k_absmax, dim3(gb), dim3(256), 0, s, p->vec, w, n, p->red.partials);
+    HIP_OK(hipGetLastError());
+    rc = sum_to_host(p, p->red.partials, gb, 1, 1, s);
+    if (rc) return rc;
+    *out = p->host_sums[0];
+    return std::isfinite(*out) ? ISAM_OK : ISAM_ENONFINITE;
+}
+
+extern "C" int isam_fista(isam_plan_t p, const float* y, float lambda, const float* w, int max_iter,
+                          float tol, double L, int add_residual, void* eta_out, isam_fista_info* info,
+                          void* stream) {
+    if (!p || !y || !eta_out || max_iter < 0 || !(lambda >= 0.f) || !(tol >= 0.f) || !std::isfinite(L))
+        return ISAM_EINVAL;
+    const size_t n = (size_t)p->nx * p->nk;
+    if (overlaps(y, n * 4, eta_out, n * 8)) return ISAM_EALIAS;
+    if (w && overlaps(w, n * 4, eta_out, n * 8)) return ISAM_EALIAS;
+    hipStream_t s = (hipStream_t)stream;
+    if (L <= 0) {
+        const int rc = isam_lipschitz(p, 50, 0, nullptr, &L, stream);
+        if (rc) return rc;
+    }
+    float2* z = (float2*)eta_out;
+    const int gb = grid_for(n);
+    hipLaunchKernelGGL(k_zero, dim3(gb), dim3(256), 0, s, z, n);
+    hipLaunchKernelGGL(k_zero, dim3(gb), dim3(256), 0, s, p->fista_hat, n);
+    HIP_OK(hipGetLastError());
+    const int rb = lat_blocks(p, 1), fb = lat_blocks(p, 0);
+    float* part_r = p->red.partials;                       // residual pass, slot 0
+    float* part_f = p->red.partials + (size_t)rb * kRedSlots;   // update pass, slots 0..3
+    if (rb + fb > p->red.maxBlocks) return ISAM_EUNSUPPORTED;
+    FistaStep fs;
+    fs.step = (float)(1.0 / L);
+    fs.lam = lambda;
+    fs.norms = tol > 0.f;
+    double t = 1.0, rel_res = -1.0;
+    int k = 0, status = ISAM_OK;
+    for (k = 1; k <= max_iter; ++k) {
+        HIP_OK(nufft_fwd(p, p->fista_hat, p->zh, s));
+        HIP_OK(lat_resid(p, p->zh, y, p->rh, part_r, s));
+        HIP_OK(nufft_adj(p, p->rh, p->ghat, s));
+        const double t_next = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
+        fs.beta = (float)((t - 1.0) / t_next);
+        HIP_OK(lat_fista(p, p->fista_hat, p->ghat, z, w, fs, part_f, s));
+        if (fs.norms) {
+            const int rc = sum_to_host(p, part_f, fb, 4, 0, s);
+            if (rc) return rc;
+            const double* h = p->host_sums;
+            if (!std::isfinite(h[0]) || !std::isfinite(h[1]) || !std::isfinite(h[2])) {
+                status = ISAM_ENONFINITE;
+                break;
+            }
+            rel_res = std::sqrt(h[0]) / (std::max(std::sqrt(h[1]), std::sqrt(h[2])) + 1e-12);
+            if (rel_res < tol) break;
+        }
+        t = t_next;
+    }
+    const int iters_run = std::min(k, max_iter);
+    double resid2 = 0.0, l1 = 0.0;
+    if (max_iter > 0) {
+        int rc = sum_to_host(p, part_r, rb, 1, 0, s);
+        if (rc) return rc;
+        resid2 = p->host_sums[0];
+        rc = sum_to_host(p, part_f, fb, 4, 0, s);
+        if (rc) return rc;
+        l1 = p->host_sums[3];
+        if (!std::isfinite(resid2) || !std::isfinite(l1)) status = ISAM_ENONFINITE;
+    }
+    if (add_residual && status == ISAM_OK) {
+        // z += (1/L) A^H (y - A z)  ==  z -= (1/L) A^H (A z - y)
+        int rc = normal_impl(p, z, y, p->vec, s);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_axpy, dim3(gb), dim3(256), 0, s, z, p->vec, (float)(1.0 / L), n);
+        HIP_OK(hipGetLastError());
+    }
+    HIP_OK(hipStreamSynchronize(s));
+    if (info) {
+        info->iters_run = iters_run;
+        info->status = status;
+        info->rel_res = rel_res;
+        info->resid2 = resid2;
+        info->l1 = l1;
+        info->L = L;
+    }
+    return status;
+}

@@ -1,0 +1,455 @@
+// Plan construction: validation, workspace, and the FP64 tables of the operator.
+//
+// Tables (all built on the device in FP64, stored in FP32 where the hot path reads them):
+//   q_l^2, B(q_l)                       lateral frequencies and beam filter (Eq. 3, 16)
+//   e^{i phi(k_n)} e^{2 i k_n z_f}      dispersion phase (Eq. 7, 13) and focal reference
+//   s_m                                 Kaiser-Bessel scaling of the NUFFT
+//   u_j(tau)                            min-max interpolation weights as a piecewise cubic in tau
+//   twiddles                            exp(-2 pi i e / N) for the depth and lateral FFTs
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "common.hpp"
+#include "plan.hpp"
+
+using namespace isam;
+
+extern "C" const char* isam_strerror(int code) {
+    switch (code) {
+        case ISAM_OK: return "success";
+        case ISAM_EINVAL: return "invalid argument";
+        case ISAM_EALIAS: return "output aliases an input";
+        case ISAM_EUNSUPPORTED: return "unsupported geometry or parameter";
+        case ISAM_ENOMEM: return "device out of memory";
+        case ISAM_ENODEV: return "no HIP device";
+        case ISAM_EHIP: return "HIP runtime error";
+        case ISAM_ENONFINITE: return "non-finite value in FISTA";
+        default: return "unknown error";
+    }
+}
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+bool is_pow2(long n) { return n > 0 && (n & (n - 1)) == 0; }
+
+struct TableArgs {
+    int nx, nk, K;
+    double dx, waist, kc, dk, a2, a3, zf, beta;
+    double* q2;
+    float* Bl;
+    float2* En;
+    float* sm;
+    float2* twK;
+    float2* twX;
+};
+
+// Kaiser-Bessel scaling s_m = Psi(0) / Psi(m / K), Psi(u) = sinh(a) / a, a = sqrt(beta^2 - (pi J u)^2).
+__device__ double kb_scale(double m, int K, double beta) {
+    const double u = m / K;
+    const double a = sqrt(beta * beta - (kPi * kJ * u) * (kPi * kJ * u));
+    return (sinh(beta) / beta) * (a / sinh(a));
+}
+
+__global__ void k_tables(TableArgs a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < a.nx) {
+        const int l = (i < (a.nx + 1) / 2) ? i : i - a.nx;       // FFT order
+        const double q = 2.0 * kPi * l / (a.nx * a.dx);
+        a.q2[i] = q * q;
+        a.Bl[i] = (float)exp(-q * q * a.waist * a.waist / 8.0);
+        double sn, cs;
+        sincospi(-2.0 * i / a.nx, &sn, &cs);
+        a.twX[i] = make_float2((float)cs, (float)sn);
+    }
+    if (i < a.nk) {
+        const double d = (i - a.nk / 2) * a.dk;                   // k_n - k0
+        const double k = a.kc + d;
+        double psi = a.a2 * d * d + a.a3 * d * d * d + 2.0 * k * a.zf;
+        psi -= 2.0 * kPi * rint(psi / (2.0 * kPi));
+        double sn, cs;
+        sincos(psi, &sn, &cs);
+        const double norm = 1.0 / sqrt((double)a.nk);
+        a.En[i] = make_float2((float)(cs * norm), (float)(sn * norm));
+        a.sm[i] = (float)kb_scale(i - a.nk / 2, a.K, a.beta);
+    }
+    if (i < a.K) {
+        double sn, cs;
+        sincospi(-2.0 * i / a.K, &sn, &cs);
+        a.twK[i] = make_float2((float)cs, (float)sn);
+    }
+}
+
+// Sums over the object rows m in [-nz/2, nz/2) needed by the least-squares system
+// of the min-max interpolator:
+//   rho(x)  = sum_m s_m exp(2 pi i x m / K)       at x = tau + J/2 - j  (C^H b)
+//   gram(d) = sum_m s_m^2 exp(2 pi i d m / K)     for d in (-J, J)      (C^H C)
+// One block per value, FP64 tree reduction.
+struct SumArgs {
+    int nk, K;
+    double beta;
+    double nodes[4];        // cubic fit nodes in a piece, local coordinate in [0, 1]
+    double* out;            // [(nrho + ngram) * 2]
+};
+
+__global__ void k_minmax_sums(SumArgs a) {
+    constexpr int nrho = kPieces * 4 * kJ;
+    const int b = blockIdx.x;
+    double x;
+    int power;
+    if (b < nrho) {
+        const int nd = b / kJ, j = b % kJ + 1;
+        const int p = nd / 4, node = nd % 4;
+        const double tau = (p + a.nodes[node]) / kPieces;
+        x = tau + kJ / 2 - j;
+        power = 1;
+    } else {
+        x = (b - nrho) - (kJ - 1);
+        power = 2;
+    }
+    double re = 0.0, im = 0.0;
+    for (int i = threadIdx.x; i < a.nk; i += blockDim.x) {
+        const double m = i - a.nk / 2;
+        double s = kb_scale(m, a.K, a.beta);
+        if (power == 2) s *= s;
+        double sn, cs;
+        sincospi(2.0 * x * m / a.K, &sn, &cs);
+        re += s * cs;
+        im += s * sn;
+    }
+    __shared__ double sre[256], sim[256];
+    sre[threadIdx.x] = re;
+    sim[threadIdx.x] = im;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            sre[threadIdx.x] += sre[threadIdx.x + w];
+            sim[threadIdx.x] += sim[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        a.out[2 * b] = sre[0];
+        a.out[2 * b + 1] = sim[0];
+    }
+}
+
+struct FitArgs {
+    int K, mi;
+    double nodes[4];
+    double vinv[16];        // inverse Vandermonde of the nodes: coef[q] = sum_i vinv[q*4+i] f(node_i)
+    const double* sums;
+    float2* wtab;
+};
+
+// Per piece: solve (C^H C) u = C^H b(tau) at the four nodes by complex Cholesky,
+// apply the focal phase exp(-2 pi i mi (tau + J/2 - j) / K), fit a cubic per tap.
+__global__ void k_minmax_fit(FitArgs a) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= kPieces) return;
+    constexpr int nrho = kPieces * 4 * kJ;
+    double Lr[kJ][kJ], Li[kJ][kJ];
+    // G[r][c] = gram(c - r); Cholesky G = L L^H (lower L, real positive diagonal)
+    for (int r = 0; r < kJ; ++r) {
+        for (int c = 0; c <= r; ++c) {
+            const int d = c - r + (kJ - 1);
+            double gr = a.sums[2 * (nrho + d)], gi = a.sums[2 * (nrho + d) + 1];
+            // subtract sum_k L[r][k] conj(L[c][k])
+            for (int k = 0; k < c; ++k) {
+                gr -= Lr[r][k] * Lr[c][k] + Li[r][k] * Li[c][k];
+                gi -= Li[r][k] * Lr[c][k] - Lr[r][k] * Li[c][k];
+            }
+            if (r == c) {
+                Lr[r][r] = sqrt(gr);
+                Li[r][r] = 0.0;
+            } else {
+                Lr[r][c] = gr / Lr[c][c];
+                Li[r][c] = gi / Lr[c][c];
+            }
+        }
+    }
+    double ur[4][kJ], ui[4][kJ];
+    for (int node = 0; node < 4; ++node) {
+        const int nd = p * 4 + node;
+        double yr[kJ], yi[kJ];
+        for (int r = 0; r < kJ; ++r) {            // forward substitution L y = rho
+            double sr = a.sums[2 * (nd * kJ + r)], si = a.sums[2 * (nd * kJ + r) + 1];
+            for (int k = 0; k < r; ++k) {
+                sr -= Lr[r][k] * yr[k] - Li[r][k] * yi[k];
+                si -= Lr[r][k] * yi[k] + Li[r][k] * yr[k];
+            }
+            yr[r] = sr / Lr[r][r];
+            yi[r] = si / Lr[r][r];
+        }
+        for (int r = kJ - 1; r >= 0; --r) {       // back substitution L^H u = y
+            double sr = yr[r], si = yi[r];
+            for (int k = r + 1; k < kJ; ++k) {     // (L^H)[r][k] = conj(L[k][r])
+                sr -= Lr[k][r] * ur[node][k] + Li[k][r] * ui[node][k];
+                si -= Lr[k][r] * ui[node][k] - Li[k][r] * ur[node][k];
+            }
+            ur[node][r] = sr / Lr[r][r];
+            ui[node][r] = si / Lr[r][r];
+        }
+        const double tau = (p + a.nodes[node]) / kPieces;
+        for (int r = 0; r < kJ; ++r) {
+            const int j = r + 1;
+            // phase exp(-2 pi i mi (tau + J/2 - j) / K), argument reduced exactly in the integer part
+            const long long ip = ((long long)a.mi * (kJ / 2 - j)) % a.K;
+            const double ang = -2.0 * ((double)ip + a.mi * tau) / a.K;
+            double sn, cs;
+            sincospi(ang, &sn, &cs);
+            const double xr = ur[node][r] * cs - ui[node][r] * sn;
+            const double xi = ur[node][r] * sn + ui[node][r] * cs;
+            ur[node][r] = xr;
+            ui[node][r] = xi;
+        }
+    }
+    for (int r = 0; r < kJ; ++r) {
+        for (int q = 0; q < 4; ++q) {
+            double cr = 0.0, ci = 0.0;
+            for (int node = 0; node < 4; ++node) {
+                cr += a.vinv[q * 4 + node] * ur[node][r];
+                ci += a.vinv[q * 4 + node] * ui[node][r];
+            }
+            a.wtab[(p * kJ + r) * 4 + q] = make_float2((float)cr, (float)ci);
+        }
+    }
+}
+
+// Chebyshev nodes of [0, 1] and the inverse of their Vandermonde matrix (Gauss-Jordan, FP64).
+void cubic_nodes(double nodes[4], double vinv[16]) {
+    double V[4][8];
+    for (int i = 0; i < 4; ++i) {
+        nodes[i] = 0.5 * (1.0 - cos((2 * i + 1) * kPi / 8.0));
+        double x = 1.0;
+        for (int k = 0; k < 4; ++k) {
+            V[i][k] = x;
+            x *= nodes[i];
+            V[i][4 + k] = (i == k) ? 1.0 : 0.0;
+        }
+    }
+    for (int c = 0; c < 4; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < 4; ++r)
+            if (fabs(V[r][c]) > fabs(V[piv][c])) piv = r;
+        for (int k = 0; k < 8; ++k) std::swap(V[c][k], V[piv][k]);
+        const double d = V[c][c];
+        for (int k = 0; k < 8; ++k) V[c][k] /= d;
+        for (int r = 0; r < 4; ++r) {
+            if (r == c) continue;
+            const double f = V[r][c];
+            for (int k = 0; k < 8; ++k) V[r][k] -= f * V[c][k];
+        }
+    }
+    // V^{-1}[q][i] maps values at nodes to monomial coefficient q
+    for (int q = 0; q < 4; ++q)
+        for (int i = 0; i < 4; ++i) vinv[q * 4 + i] = V[q][4 + i];
+}
+
+int validate(const isam_geometry* g) {
+    if (!g) return ISAM_EINVAL;
+    if (g->nx < 1 || g->ny < 1 || g->nk < 2) return ISAM_EINVAL;
+    if (g->J < 2 || g->J > 16 || (g->J & 1)) return ISAM_EINVAL;
+    if (g->osf < 1) return ISAM_EINVAL;
+    if ((g->nk & 1) || g->nk < 2 * g->J) return ISAM_EINVAL;
+    const double vals[] = {g->dx, g->lambda_c, g->dlambda, g->waist, g->z_focus, g->a2, g->a3,
+                           g->kb_beta};
+    for (double v : vals)
+        if (!std::isfinite(v)) return ISAM_EINVAL;
+    if (!(g->dx > 0) || !(g->lambda_c > 0) || !(g->dlambda > 0) || g->waist < 0) return ISAM_EINVAL;
+    if (!(g->dlambda < g->lambda_c)) return ISAM_EINVAL;
+    if (g->ny != 1) return ISAM_EUNSUPPORTED;
+    if (g->J != kJ || g->osf != 2) return ISAM_EUNSUPPORTED;
+    if (!is_pow2(g->nx) || g->nx > 2048) return ISAM_EUNSUPPORTED;
+    if (!is_pow2(g->nk) || g->nk > 4096) return ISAM_EUNSUPPORTED;
+    const double beta = g->kb_beta > 0 ? g->kb_beta : 2.34 * g->J;
+    if (!(beta > kPi * g->J / (2.0 * g->osf))) return ISAM_EINVAL;   // scaling defined on all rows
+    return ISAM_OK;
+}
+
+void derive(isam_plan_s* p, const isam_geometry* g) {
+    p->g = *g;
+    p->nx = g->nx;
+    p->nk = g->nk;
+    p->K = g->osf * g->nk;
+    p->nh = g->nx / 2 + 1;
+    p->kc = 2.0 * kPi / g->lambda_c;
+    p->band = 2.0 * kPi * g->dlambda / (g->lambda_c * g->lambda_c);
+    p->dk = p->band / g->nk;
+    p->dz = kPi / p->band;
+    p->cT = p->dz * p->K / (2.0 * kPi);
+    p->beta = g->kb_beta > 0 ? g->kb_beta : 2.34 * g->J;
+    p->mf = g->z_focus / p->dz;
+    p->mi = (int)std::lrint(p->mf);
+    p->mr = p->mf - p->mi;
+    if (std::fabs(p->mr) < 1e-9) p->mr = 0.0;
+}
+
+#define HIP_TRY(x)                                  \
+    do {                                            \
+        if ((x) != hipSuccess) return ISAM_EHIP;    \
+    } while (0)
+
+int build_calibrated_tables(isam_plan_s* p, hipStream_t s) {
+    TableArgs a;
+    a.nx = p->nx;
+    a.nk = p->nk;
+    a.K = p->K;
+    a.dx = p->g.dx;
+    a.waist = p->g.waist;
+    a.kc = p->kc;
+    a.dk = p->dk;
+    a.a2 = p->g.a2;
+    a.a3 = p->g.a3;
+    a.zf = p->g.z_focus;
+    a.beta = p->beta;
+    a.q2 = p->q2;
+    a.Bl = p->Bl;
+    a.En = p->En;
+    a.sm = p->sm;
+    a.twK = p->twK;
+    a.twX = p->twX;
+    const int n = std::max(p->K, std::max(p->nx, p->nk));
+    hipLaunchKernelGGL(k_tables, dim3((n + 255) / 256), dim3(256), 0, s, a);
+    HIP_TRY(hipGetLastError());
+
+    SumArgs sa;
+    sa.nk = p->nk;
+    sa.K = p->K;
+    sa.beta = p->beta;
+    FitArgs fa;
+    cubic_nodes(fa.nodes, fa.vinv);
+    std::memcpy(sa.nodes, fa.nodes, sizeof(sa.nodes));
+    sa.out = p->wscratch;
+    const int nsums = kPieces * 4 * kJ + (2 * kJ - 1);
+    hipLaunchKernelGGL(k_minmax_sums, dim3(nsums), dim3(256), 0, s, sa);
+    HIP_TRY(hipGetLastError());
+    fa.K = p->K;
+    fa.mi = p->mi;
+    fa.sums = p->wscratch;
+    fa.wtab = p->wtab;
+    hipLaunchKernelGGL(k_minmax_fit, dim3(1), dim3(64), 0, s, fa);
+    HIP_TRY(hipGetLastError());
+    return ISAM_OK;
+}
+
+template <typename T>
+int dalloc(T** ptr, size_t n) {
+    if (hipMalloc((void**)ptr, n * sizeof(T)) != hipSuccess) {
+        *ptr = nullptr;
+        return ISAM_ENOMEM;
+    }
+    return ISAM_OK;
+}
+
+void release(isam_plan_s* p) {
+    void* ptrs[] = {p->q2, p->Bl, p->En, p->sm, p->wtab, p->twK, p->twX, p->wscratch,
+                    p->etahat, p->zh, p->rh, p->ghat, p->fista_hat, p->vec, p->sbuf,
+                    p->red.partials, p->red.sums};
+    for (void* q : ptrs)
+        if (q) (void)hipFree(q);
+    if (p->host_sums) (void)hipHostFree(p->host_sums);
+    delete p;
+}
+
+}  // namespace
+
+isam::NufftArgs isam_plan_s::nufft_args() const {
+    isam::NufftArgs a;
+    a.nx = nx;
+    a.nk = nk;
+    a.K = K;
+    a.mi = mi;
+    a.has_frac = mr != 0.0;
+    a.mr_over_K = mr / K;
+    a.kc = kc;
+    a.dk = dk;
+    a.cT = cT;
+    a.q2 = q2;
+    a.Bl = Bl;
+    a.En = En;
+    a.sm = sm;
+    a.wtab = wtab;
+    a.tw = twK;
+    return a;
+}
+
+extern "C" int isam_plan(const isam_geometry* g, void* stream, isam_plan_t* out) {
+    if (!out) return ISAM_EINVAL;
+    *out = nullptr;
+    int rc = validate(g);
+    if (rc != ISAM_OK) return rc;
+    isam_plan_s probe;
+    derive(&probe, g);
+    if (!isam::nufft_span_ok(&probe)) return ISAM_EUNSUPPORTED;
+
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return ISAM_ENODEV;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return ISAM_ENODEV;
+
+    isam_plan_s* p = new (std::nothrow) isam_plan_s();
+    if (!p) return ISAM_ENOMEM;
+    derive(p, g);
+    p->device = dev;
+    const size_t full = (size_t)p->nx * p->nk, half = (size_t)p->nh * p->nk;
+    p->red.maxBlocks = std::max(std::max(p->nx, p->nk), 2048) + 64;
+    const int nsums = kPieces * 4 * kJ + (2 * kJ - 1);
+    rc = ISAM_OK;
+    rc = rc ? rc : dalloc(&p->q2, p->nx);
+    rc = rc ? rc : dalloc(&p->Bl, p->nx);
+    rc = rc ? rc : dalloc(&p->En, p->nk);
+    rc = rc ? rc : dalloc(&p->sm, p->nk);
+    rc = rc ? rc : dalloc(&p->wtab, kWtabEntries);
+    rc = rc ? rc : dalloc(&p->twK, p->K);
+    rc = rc ? rc : dalloc(&p->twX, std::max(p->nx, 1));
+    rc = rc ? rc : dalloc(&p->wscratch, 2 * nsums);
+    rc = rc ? rc : dalloc(&p->etahat, full);
+    rc = rc ? rc : dalloc(&p->zh, half);
+    rc = rc ? rc : dalloc(&p->rh, half);
+    rc = rc ? rc : dalloc(&p->ghat, full);
+    rc = rc ? rc : dalloc(&p->fista_hat, full);
+    rc = rc ? rc : dalloc(&p->vec, full);
+    rc = rc ? rc : dalloc(&p->sbuf, full);
+    rc = rc ? rc : dalloc(&p->red.partials, (size_t)p->red.maxBlocks * kRedSlots);
+    rc = rc ? rc : dalloc(&p->red.sums, kRedSlots);
+    if (rc == ISAM_OK && hipHostMalloc((void**)&p->host_sums, kRedSlots * sizeof(double)) != hipSuccess)
+        rc = ISAM_ENOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    if (rc == ISAM_OK) rc = build_calibrated_tables(p, s);
+    if (rc == ISAM_OK && hipStreamSynchronize(s) != hipSuccess) rc = ISAM_EHIP;
+    if (rc != ISAM_OK) {
+        release(p);
+        return rc;
+    }
+    *out = p;
+    return ISAM_OK;
+}
+
+extern "C" int isam_set_calibration(isam_plan_t p, double a2, double a3, double z_focus, void* stream) {
+    if (!p) return ISAM_EINVAL;
+    if (!std::isfinite(a2) || !std::isfinite(a3) || !std::isfinite(z_focus)) return ISAM_EINVAL;
+    isam_geometry g = p->g;
+    g.a2 = a2;
+    g.a3 = a3;
+    g.z_focus = z_focus;
+    derive(p, &g);
+    hipStream_t s = (hipStream_t)stream;
+    int rc = build_calibrated_tables(p, s);
+    if (rc == ISAM_OK && hipStreamSynchronize(s) != hipSuccess) rc = ISAM_EHIP;
+    return rc;
+}
+
+extern "C" void isam_destroy(isam_plan_t p) {
+    if (p) release(p);
+}
+
+extern "C" int isam_plan_dims(isam_plan_t p, int32_t* nx, int32_t* nk, int32_t* K) {
+    if (!p) return ISAM_EINVAL;
+    if (nx) *nx = p->nx;
+    if (nk) *nk = p->nk;
+    if (K) *K = p->K;
+    return ISAM_OK;
+}

@@ -1,0 +1,231 @@
+"""Thin ctypes binding of libisam.so (the MI355X full-range ISAM operator and FISTA solve).
+
+Argument marshalling only: every step of the computation runs in the library's
+HIP kernels.  PyTorch supplies device memory (tensor data pointers) and the
+current HIP stream.  There is no fallback: if the library is missing or no GPU
+is visible, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libisam.so")
+
+ISAM_OK = 0
+ERRORS = {
+    -1: "ISAM_EINVAL", -2: "ISAM_EALIAS", -3: "ISAM_EUNSUPPORTED", -4: "ISAM_ENOMEM",
+    -5: "ISAM_ENODEV", -6: "ISAM_EHIP", -7: "ISAM_ENONFINITE",
+}
+
+# Every symbol the public header declares.
+EXPORTS = (
+    "isam_plan", "isam_set_calibration", "isam_forward", "isam_adjoint", "isam_normal",
+    "isam_lipschitz", "isam_lambda_max", "isam_fista", "isam_destroy", "isam_strerror",
+    "isam_plan_dims",
+)
+
+
+class IsamError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {ERRORS.get(code, code)} ({_strerror(code)})")
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nk", ctypes.c_int32),
+        ("dx", ctypes.c_double), ("dy", ctypes.c_double),
+        ("lambda_c", ctypes.c_double), ("dlambda", ctypes.c_double),
+        ("waist", ctypes.c_double), ("z_focus", ctypes.c_double),
+        ("a2", ctypes.c_double), ("a3", ctypes.c_double),
+        ("J", ctypes.c_int32), ("osf", ctypes.c_int32), ("kb_beta", ctypes.c_double),
+    ]
+
+    @classmethod
+    def of(cls, o, **overrides) -> "Geometry":
+        """From any record carrying nx, nk, dx, lambda_c, dlambda, waist, z_focus, a2, a3."""
+        vals = dict(nx=o.nx, ny=1, nk=o.nk, dx=o.dx, dy=getattr(o, "dy", o.dx),
+                    lambda_c=o.lambda_c, dlambda=o.dlambda, waist=o.waist, z_focus=o.z_focus,
+                    a2=o.a2, a3=o.a3, J=getattr(o, "J", 6), osf=getattr(o, "osf", 2),
+                    kb_beta=getattr(o, "kb_beta", 0.0))
+        vals.update(overrides)
+        return cls(**vals)
+
+
+class FistaInfo(ctypes.Structure):
+    _fields_ = [
+        ("iters_run", ctypes.c_int32), ("status", ctypes.c_int32), ("rel_res", ctypes.c_double),
+        ("resid2", ctypes.c_double), ("l1", ctypes.c_double), ("L", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def load_library() -> ctypes.CDLL:
+    """Load libisam.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "or python -m paper_1905_06058_amd.build")
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, i32, dbl, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_float
+        lib.isam_plan.argtypes = [ctypes.POINTER(Geometry), vp, ctypes.POINTER(vp)]
+        lib.isam_set_calibration.argtypes = [vp, dbl, dbl, dbl, vp]
+        lib.isam_forward.argtypes = [vp, vp, vp, vp]
+        lib.isam_adjoint.argtypes = [vp, vp, vp, vp]
+        lib.isam_normal.argtypes = [vp, vp, vp, vp]
+        lib.isam_lipschitz.argtypes = [vp, ctypes.c_int, ctypes.c_uint64, vp, ctypes.POINTER(dbl), vp]
+        lib.isam_lambda_max.argtypes = [vp, vp, vp, ctypes.POINTER(dbl), vp]
+        lib.isam_fista.argtypes = [vp, vp, f32, vp, ctypes.c_int, f32, dbl, ctypes.c_int, vp,
+                                   ctypes.POINTER(FistaInfo), vp]
+        lib.isam_destroy.argtypes = [vp]
+        lib.isam_destroy.restype = None
+        lib.isam_strerror.argtypes = [ctypes.c_int]
+        lib.isam_strerror.restype = ctypes.c_char_p
+        lib.isam_plan_dims.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        for name in EXPORTS:
+            if name not in ("isam_destroy", "isam_strerror"):
+                getattr(lib, name).restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _strerror(code: int) -> str:
+    try:
+        return load_library().isam_strerror(code).decode()
+    except Exception:  # pragma: no cover - message formatting only
+        return "?"
+
+
+def _check(code: int, what: str) -> None:
+    if code != ISAM_OK:
+        raise IsamError(code, what)
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_tensor(t: torch.Tensor, dtype, shape, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor of shape {tuple(shape)}")
+    return t
+
+
+@dataclass
+class FistaResult:
+    eta: torch.Tensor
+    iters: int
+    status: int
+    rel_res: float
+    resid2: float
+    l1: float
+    L: float
+
+
+class Plan:
+    """An ISAM operator plan for one geometry on the current device."""
+
+    def __init__(self, geometry, stream=None):
+        lib = load_library()
+        g = geometry if isinstance(geometry, Geometry) else Geometry.of(geometry)
+        self.geometry = g
+        self.nx, self.nk = int(g.nx), int(g.nk)
+        self._h = ctypes.c_void_p()
+        _check(lib.isam_plan(ctypes.byref(g), _stream(stream), ctypes.byref(self._h)), "isam_plan")
+        self._lib = lib
+
+    @property
+    def shape(self):
+        return (self.nx, self.nk)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.isam_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_calibration(self, a2: float, a3: float, z_focus: float, stream=None) -> None:
+        _check(self._lib.isam_set_calibration(self._h, a2, a3, z_focus, _stream(stream)),
+               "isam_set_calibration")
+
+    def forward(self, eta: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        _dev_tensor(eta, torch.complex64, self.shape, "eta")
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float32, device=eta.device)
+        _dev_tensor(out, torch.float32, self.shape, "out")
+        _check(self._lib.isam_forward(self._h, eta.data_ptr(), out.data_ptr(), _stream(stream)),
+               "isam_forward")
+        return out
+
+    def adjoint(self, r: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        _dev_tensor(r, torch.float32, self.shape, "r")
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.complex64, device=r.device)
+        _dev_tensor(out, torch.complex64, self.shape, "out")
+        _check(self._lib.isam_adjoint(self._h, r.data_ptr(), out.data_ptr(), _stream(stream)),
+               "isam_adjoint")
+        return out
+
+    def normal(self, eta: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        _dev_tensor(eta, torch.complex64, self.shape, "eta")
+        if out is None:
+            out = torch.empty_like(eta)
+        _dev_tensor(out, torch.complex64, self.shape, "out")
+        _check(self._lib.isam_normal(self._h, eta.data_ptr(), out.data_ptr(), _stream(stream)),
+               "isam_normal")
+        return out
+
+    def lipschitz(self, iters: int = 50, seed: int = 0, x0: torch.Tensor | None = None, stream=None) -> float:
+        L = ctypes.c_double()
+        ptr = None
+        if x0 is not None:
+            ptr = _dev_tensor(x0, torch.complex64, self.shape, "x0").data_ptr()
+        _check(self._lib.isam_lipschitz(self._h, iters, seed, ptr, ctypes.byref(L), _stream(stream)),
+               "isam_lipschitz")
+        return L.value
+
+    def lambda_max(self, y: torch.Tensor, w: torch.Tensor | None = None, stream=None) -> float:
+        _dev_tensor(y, torch.float32, self.shape, "y")
+        wp = None if w is None else _dev_tensor(w, torch.float32, self.shape, "w").data_ptr()
+        out = ctypes.c_double()
+        _check(self._lib.isam_lambda_max(self._h, y.data_ptr(), wp, ctypes.byref(out), _stream(stream)),
+               "isam_lambda_max")
+        return out.value
+
+    def fista(self, y: torch.Tensor, lam: float, iters: int, w: torch.Tensor | None = None,
+              tol: float = 0.0, L: float = 0.0, add_residual: bool = False,
+              out: torch.Tensor | None = None, stream=None) -> FistaResult:
+        _dev_tensor(y, torch.float32, self.shape, "y")
+        wp = None if w is None else _dev_tensor(w, torch.float32, self.shape, "w").data_ptr()
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.complex64, device=y.device)
+        _dev_tensor(out, torch.complex64, self.shape, "out")
+        info = FistaInfo()
+        code = self._lib.isam_fista(self._h, y.data_ptr(), float(lam), wp, int(iters), float(tol),
+                                    float(L), int(bool(add_residual)), out.data_ptr(),
+                                    ctypes.byref(info), _stream(stream))
+        _check(code, "isam_fista")
+        return FistaResult(out, info.iters_run, info.status, info.rel_res, info.resid2, info.l1, info.L)

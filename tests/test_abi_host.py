@@ -1,0 +1,100 @@
+"""Host-side checks of the C ABI: the library loads, exports what include/isam.h declares,
+and rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1905_06058_amd as P
+import phantoms as ph
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(P.LIB_PATH):
+        from paper_1905_06058_amd import build
+        build.build()
+    return P.load_library()
+
+
+def header_symbols():
+    text = open(os.path.join(ROOT, "include", "isam.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(isam_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = header_symbols()
+    assert "isam_plan" in names and "isam_fista" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(P.EXPORTS) == names
+
+
+def test_strerror_is_static_and_total(lib):
+    for code in [0, -1, -2, -3, -4, -5, -6, -7, 99, -100]:
+        s = lib.isam_strerror(code)
+        assert isinstance(s, bytes) and len(s) > 0
+
+
+def _geom(**kw):
+    return P.Geometry.of(ph.workload("tiny").optics, **kw)
+
+
+def _plan_rc(lib, g):
+    h = ctypes.c_void_p()
+    rc = lib.isam_plan(ctypes.byref(g) if g is not None else None, None, ctypes.byref(h))
+    if rc == 0:
+        lib.isam_destroy(h)
+    return rc
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(nk=255), -1),            # odd
+    (dict(nk=8), -1),              # fewer than 2J samples
+    (dict(J=5), -1),
+    (dict(J=8), -3),
+    (dict(osf=3), -3),
+    (dict(nx=0), -1),
+    (dict(nx=96), -3),             # not a power of two
+    (dict(nk=8192), -3),
+    (dict(nx=4096), -3),
+    (dict(ny=2), -3),
+    (dict(dx=0.0), -1),
+    (dict(dlambda=-1e-9), -1),
+    (dict(a2=float("nan")), -1),
+    (dict(z_focus=float("inf")), -1),
+    (dict(kb_beta=1.0), -1),        # scaling undefined at the outer rows
+])
+def test_plan_rejects_bad_geometry(lib, kw, code):
+    assert _plan_rc(lib, _geom(**kw)) == code
+
+
+def test_plan_null_arguments(lib):
+    g = _geom()
+    assert lib.isam_plan(None, None, ctypes.byref(ctypes.c_void_p())) == -1
+    assert lib.isam_plan(ctypes.byref(g), None, None) == -1
+
+
+def test_entry_points_reject_null_plan(lib):
+    buf = ctypes.create_string_buffer(64)
+    assert lib.isam_forward(None, buf, buf, None) == -1
+    assert lib.isam_adjoint(None, buf, buf, None) == -1
+    assert lib.isam_normal(None, buf, buf, None) == -1
+    L = ctypes.c_double()
+    assert lib.isam_lipschitz(None, 10, 0, None, ctypes.byref(L), None) == -1
+    assert lib.isam_lambda_max(None, buf, None, ctypes.byref(L), None) == -1
+    assert lib.isam_fista(None, buf, 0.1, None, 1, 0.0, 1.0, 0, buf, None, None) == -1
+    assert lib.isam_set_calibration(None, 0.0, 0.0, 0.0, None) == -1
+    assert lib.isam_plan_dims(None, None, None, None) == -1
+    lib.isam_destroy(None)
+
+
+def test_valid_geometry_without_device_reports_enodev(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    assert _plan_rc(lib, _geom()) == -5
