@@ -1,0 +1,242 @@
+#!/usr/bin/env python3
+"""Throughput of the MI355X full-range ISAM hot path on the 1024 x 2048 B-scan.
+
+A step is one FISTA iteration of the MBIR solve (Alg. 1): forward operator
+A = Re(K^ .), residual, adjoint A^H, gradient step, weighted soft threshold and
+momentum, on a synthetic 1024 A-scan x 2048-sample B-scan (5 layers + 2000 point
+scatterers on both sides of zero delay, 40 pi / 8 pi dispersion, 25 dB SNR).
+The same run also times A.A^H operator pairs (isam_forward + isam_adjoint).
+
+Prints one JSON line.  Inputs are resident in device memory before timing starts.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0       # MI355X HBM3E
+METRIC = "A^H·A op pairs/s + FISTA iter/s, 1024×2048 B-scan FP32 vs plain; %HBM peak"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCES = ["paper_1905_06058_amd/csrc/" + f for f in
+                  ("common.hpp", "fft.hpp", "plan.hpp", "lateral.hip", "nufft.hip", "solver.hip")]
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200, help="timed FISTA iterations")
+    ap.add_argument("--warmup", type=int, default=20, help="untimed FISTA iterations before timing")
+    ap.add_argument("--pairs", type=int, default=200, help="timed A.A^H pairs")
+    ap.add_argument("--workload", default="bscan")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-nx", type=int, default=64,
+                    help="A-scans of the oracle's timing sample (same depth length and optics)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle timing budget")
+    return ap.parse_args()
+
+
+def sources_digest() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def pass_bytes(nx: int, nk: int, weighted: bool) -> dict:
+    """Algorithmic HBM bytes per launch of each pass: inputs read once, outputs written once."""
+    full = nx * nk
+    half = (nx // 2 + 1) * nk
+    c, f = 8, 4
+    return {
+        "lateral_fft_fwd": 2 * c * full,
+        "nufft_fwd": c * full + c * half,
+        "lateral_c2r": c * half + f * full,
+        "lateral_r2c": f * full + c * half,
+        "nufft_adj": c * half + c * full,
+        "lateral_fft_inv": 2 * c * full,
+        "residual_pass": c * half + f * full + c * half,
+        "fista_update": 5 * c * full + (f * full if weighted else 0),
+    }
+
+
+def cpu_baseline(w, sample_nx: int, budget_s: float, iters_full: int) -> dict:
+    """The FP64 oracle's FISTA iteration rate on a sample of the workload, scaled to it."""
+    import numpy as np
+    import oracle as O
+    import phantoms as ph
+    from threadpoolctl import threadpool_limits
+
+    o = w.optics
+    sample = ph.custom_optics(sample_nx, o.nk, edge_phase2=40 * math.pi, edge_phase3=8 * math.pi,
+                              focus_rows=o.nk // 4)
+    g = O.Geometry.of(sample)
+    with threadpool_limits(limits=1):
+        op = O.Operator(g, "N")
+        rng = np.random.default_rng(w.seed)
+        eta = ph.layers(rng, g.nx, g.nk, w.n_layers) + ph.point_scatterers(
+            rng, g.nx, g.nk, max(1, w.n_points * sample_nx // o.nx))
+        y = ph.add_noise(op.A(eta), w.snr_db, w.seed)
+        lam = w.lam_frac * O.lambda_max(op, y)
+        O.fista(op, y, lam, 1.0, 1)                       # warm-up
+        n = 0
+        t0 = time.perf_counter()
+        while True:
+            n += 2
+            t1 = time.perf_counter()
+            O.fista(op, y, lam, 1.0, 2)
+            if time.perf_counter() - t0 >= budget_s or n >= iters_full:
+                break
+        dt = time.perf_counter() - t0
+    rate_sample = n / dt
+    return {
+        "value": rate_sample * sample_nx / o.nx,
+        "unit": "iter/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"{n} FISTA iterations of the FP64 oracle (min-max NUFFT mode, cached interpolation "
+                   f"matrices) on {sample_nx} of the {o.nx} A-scans ({sample_nx}x{o.nk}, same optics), "
+                   f"{dt:.1f} s at {rate_sample:.3f} iter/s, scaled by {sample_nx}/{o.nx} "
+                   f"(per-iteration work is linear in the A-scan count up to the lateral FFT's log factor)"),
+    }
+
+
+def main() -> int:
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(independent B-scans shard without communication; see the design notes)", file=sys.stderr)
+        return 2
+    import numpy as np
+    import torch
+
+    import paper_1905_06058_amd as P
+    import phantoms as ph
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        return 1
+    torch.cuda.set_device(0)
+    w = ph.workload(args.workload)
+    o = w.optics
+    nx, nk = o.nx, o.nk
+    plan = P.Plan(P.Geometry.of(o))
+    eta_true = torch.from_numpy(ph.phantom(w)).to(torch.complex64).cuda()
+    s_clean = plan.forward(eta_true)
+    y = torch.from_numpy(ph.add_noise(s_clean.double().cpu().numpy(), w.snr_db, w.seed)).float().cuda()
+    L = plan.lipschitz(iters=50, seed=0)
+    lam = w.lam_frac * plan.lambda_max(y)
+    out = torch.empty((nx, nk), dtype=torch.complex64, device="cuda")
+    torch.cuda.synchronize()
+
+    # ---- FISTA: warm-up, then exactly `steps` iterations in one timed region
+    if args.warmup > 0:
+        plan.fista(y, lam, args.warmup, L=L, out=out)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    res = plan.fista(y, lam, args.steps, L=L, out=out)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    ms_per_step = 1e3 * wall / max(args.steps, 1)
+    if res.status != 0 or not math.isfinite(res.resid2):
+        print(f"bench.py: FISTA status {res.status}", file=sys.stderr)
+        return 1
+
+    # ---- operator pairs A.A^H (isam_forward then isam_adjoint)
+    x = torch.randn((nx, nk), dtype=torch.complex64, device="cuda")
+    sbuf = torch.empty((nx, nk), dtype=torch.float32, device="cuda")
+    for _ in range(20):
+        plan.forward(x, out=sbuf)
+        plan.adjoint(sbuf, out=x)
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    for _ in range(args.pairs):
+        plan.forward(x, out=sbuf)
+        plan.adjoint(sbuf, out=x)
+    torch.cuda.synchronize()
+    pair_s = (time.perf_counter() - tp) / max(args.pairs, 1)
+
+    # ---- per-pass kernel durations (HIP events on the launch stream) over a second FISTA run
+    plan.timing(True)
+    plan.fista(y, lam, args.steps, L=L, out=out)
+    passes = plan.timing(False)
+    plan.timing(True)
+    for _ in range(args.pairs):
+        plan.forward(x, out=sbuf)
+        plan.adjoint(sbuf, out=x)
+    passes_pair = plan.timing(False)
+    nbytes = pass_bytes(nx, nk, weighted=False)
+    per_pass = {}
+    for name, (ms, cnt) in list(passes.items()) + list(passes_pair.items()):
+        if cnt:
+            prev = per_pass.get(name)
+            if prev is None or cnt > prev["launches"]:
+                avg = ms / cnt
+                per_pass[name] = {"avg_us": round(1e3 * avg, 3), "launches": int(cnt),
+                                  "GBps": round(nbytes[name] / (avg * 1e-3) / 1e9, 1)}
+    fista_passes = {k: v for k, v in passes.items() if v[1]}
+    dom = max(fista_passes, key=lambda k: fista_passes[k][0])
+    dom_avg_s = fista_passes[dom][0] / fista_passes[dom][1] * 1e-3
+    achieved = nbytes[dom] / dom_avg_s / 1e9
+
+    traffic = None
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+        k = rec.get("kernels", {}).get(dom)
+        if k and rec.get("sources") == sources_digest() and rec.get("workload") == args.workload:
+            traffic = k["bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        traffic = None
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, args.cpu_sample_nx, args.cpu_seconds, args.steps)
+
+    line = {
+        "metric": METRIC,
+        "value": round(args.steps / wall, 2),
+        "unit": "iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {nx}x{nk} full-range B-scan, {w.n_layers} layers + "
+                               f"{w.n_points} scatterers, FISTA lambda={w.lam_frac}*lambda_max, tol=0",
+                   "nx": nx, "nk": nk, "J": 6, "oversampling": 2},
+        "fista_iter_per_s": round(args.steps / wall, 2),
+        "fista_gpu_ms_per_iter": round(gpu_ms / max(args.steps, 1), 5),
+        "pairs_per_s": round(1.0 / pair_s, 2),
+        "ms_per_pair": round(1e3 * pair_s, 5),
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "algorithmic_bytes_per_launch": nbytes[dom],
+                     "avg_launch_us": round(dom_avg_s * 1e6, 3)},
+        "passes": per_pass,
+        "cpu_baseline": cpu,
+        "gpu": torch.cuda.get_device_name(0),
+    }
+    print(json.dumps(line))
+    plan.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -49,7 +49,8 @@ enum {
     ISAM_EINVAL = -1,        /* bad argument: null pointer, size or non-finite optics */
     ISAM_EALIAS = -2,        /* an output aliases an input */
     ISAM_EUNSUPPORTED = -3,  /* valid but not built: J != 6, osf != 2, non power-of-two sizes,
-                                nx > 2048, nk > 4096, ny != 1, Stolt span beyond two periods */
+                                nx > 2048, nk > 4096, ny != 1, a Stolt-mapped column spanning
+                                more than 5/4 of the oversampled depth period */
     ISAM_ENOMEM = -4,        /* device allocation failed */
     ISAM_ENODEV = -5,        /* no HIP device visible */
     ISAM_EHIP = -6,          /* a HIP runtime call failed */
@@ -136,6 +137,20 @@ int isam_lambda_max(isam_plan_t p, const float* y, const float* w, double* out, 
 int isam_fista(isam_plan_t p, const float* y, float lambda, const float* w, int max_iter,
                float tol, double L, int add_residual, void* eta_out, isam_fista_info* info,
                void* stream);
+
+/* Per-pass timing (profiling support).  enable = 1 clears the accumulators and
+ * makes every later operator / FISTA call on the plan record a HIP event pair
+ * around each kernel pass on its stream; enable = 0 stops recording.  Elapsed
+ * times are summed when a call completes (calls that synchronise) or here.
+ * ms_out[ISAM_NPASS] and count_out[ISAM_NPASS] (either may be NULL) receive
+ * the summed milliseconds and launch counts per pass:
+ *   0 lateral FFT (forward)          1 Stolt NUFFT forward
+ *   2 lateral C2R                    3 lateral R2C
+ *   4 Stolt NUFFT adjoint            5 lateral FFT (inverse)
+ *   6 residual pass (C2R, -y, R2C)   7 FISTA update pass
+ * Synchronises the plan's last stream before reading. */
+#define ISAM_NPASS 8
+int isam_timing(isam_plan_t p, int enable, double* ms_out, int64_t* count_out);
 
 /* Release a plan (NULL is allowed). */
 void isam_destroy(isam_plan_t p);

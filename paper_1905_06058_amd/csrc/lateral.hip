@@ -24,25 +24,25 @@
 namespace isam {
 namespace {
 
-template <int N>
+template <int N, int C_>
 struct LatCfg {
     static constexpr int P = ilog2(N);
     static constexpr int RO = 1 << fft_radix_log(P, 0);
-    static constexpr int C = N >= 2048 ? 4 : 8;              // complex lanes per tile
+    static constexpr int C = C_;                             // complex lanes per tile
     static constexpr int NB = N / RO * C;
     static constexpr int T = NB < 64 ? 64 : (NB > 256 ? 256 : NB);
     static constexpr int SPAN = N / RO;
     // the tile, and at least room for the block-reduction scratch (4 values x 4 waves)
-    static constexpr size_t LDS = (size_t)N * C * sizeof(float2) > 256 ? (size_t)N * C * sizeof(float2) : 256;
+    static constexpr size_t LDS = (size_t)lds_size(N * C) * sizeof(float2) > 256 ? (size_t)lds_size(N * C) * sizeof(float2) : 256;
     using Fwd = LdsFft<N, C, T, -1>;
     using Inv = LdsFft<N, C, T, +1>;
     static_assert(Fwd::EPT == Inv::EPT, "layouts");
 };
 
-template <int N, int SIGN>
-__global__ __launch_bounds__(LatCfg<N>::T) void k_lat_c2c(const float2* in, float2* out, int nk,
+template <int N, int C, int SIGN>
+__global__ __launch_bounds__((LatCfg<N, C>::T)) void k_lat_c2c(const float2* in, float2* out, int nk,
                                                           const float2* __restrict__ tw, float scale) {
-    using Cf = LatCfg<N>;
+    using Cf = LatCfg<N, C>;
     using F = LdsFft<N, Cf::C, Cf::T, SIGN>;
     extern __shared__ float2 lds[];
     const int m0 = xcd_tile(blockIdx.x, gridDim.x) * Cf::C;
@@ -50,17 +50,17 @@ __global__ __launch_bounds__(LatCfg<N>::T) void k_lat_c2c(const float2* in, floa
 #pragma unroll
     for (int i = 0; i < F::BPTO; ++i) {
         int c, b;
-        if (F::outer(i, c, b)) {
+        if (F::outer(threadIdx.x, i, c, b)) {
 #pragma unroll
             for (int j = 0; j < Cf::RO; ++j)
                 v[i * Cf::RO + j] = in[(size_t)(b + j * Cf::SPAN) * nk + m0 + c];
         }
     }
-    F::run(v, lds, tw);
+    F::run(v, lds, tw, threadIdx.x);
 #pragma unroll
     for (int i = 0; i < F::BPTO; ++i) {
         int c, b;
-        if (F::outer(i, c, b)) {
+        if (F::outer(threadIdx.x, i, c, b)) {
 #pragma unroll
             for (int j = 0; j < Cf::RO; ++j)
                 out[(size_t)(b + j * Cf::SPAN) * nk + m0 + c] = cscale(v[i * Cf::RO + j], scale);
@@ -87,28 +87,28 @@ ISAM_DEV void split_store(float2* lds, const float2 (&v)[LdsFft<N, C, T, -1>::EP
 #pragma unroll
     for (int i = 0; i < F::BPTO; ++i) {
         int c, b;
-        if (F::outer(i, c, b)) {
+        if (F::outer(threadIdx.x, i, c, b)) {
 #pragma unroll
-            for (int j = 0; j < RO; ++j) lds[(b + j * SPAN) * C + c] = v[i * RO + j];
+            for (int j = 0; j < RO; ++j) lds[lds_pad((b + j * SPAN) * C + c)] = v[i * RO + j];
         }
     }
     __syncthreads();
     const float h = 0.5f * scale;
     for (int o = threadIdx.x; o < (N / 2 + 1) * C; o += T) {
         const int l = o / C, c = o % C;
-        const float2 A = lds[l * C + c];
-        const float2 B = cconj(lds[((N - l) & (N - 1)) * C + c]);
+        const float2 A = lds[lds_pad(l * C + c)];
+        const float2 B = cconj(lds[lds_pad(((N - l) & (N - 1)) * C + c)]);
         const float2 s = cadd(A, B), d = csub(A, B);
         *reinterpret_cast<float4*>(rh + (size_t)l * nk + n0 + 2 * c) =
             make_float4(s.x * h, s.y * h, d.y * h, -d.x * h);
     }
 }
 
-template <int N>
-__global__ __launch_bounds__(LatCfg<N>::T) void k_lat_c2r(const float2* __restrict__ zh,
+template <int N, int C>
+__global__ __launch_bounds__((LatCfg<N, C>::T)) void k_lat_c2r(const float2* __restrict__ zh,
                                                           float* __restrict__ s, int nk,
                                                           const float2* __restrict__ tw, float scale) {
-    using Cf = LatCfg<N>;
+    using Cf = LatCfg<N, C>;
     using F = typename Cf::Inv;
     extern __shared__ float2 lds[];
     const int n0 = xcd_tile(blockIdx.x, gridDim.x) * 2 * Cf::C;
@@ -116,17 +116,17 @@ __global__ __launch_bounds__(LatCfg<N>::T) void k_lat_c2r(const float2* __restri
 #pragma unroll
     for (int i = 0; i < F::BPTO; ++i) {
         int c, b;
-        if (F::outer(i, c, b)) {
+        if (F::outer(threadIdx.x, i, c, b)) {
 #pragma unroll
             for (int j = 0; j < Cf::RO; ++j)
                 v[i * Cf::RO + j] = hermitian_pair<N>(zh, nk, b + j * Cf::SPAN, n0 + 2 * c);
         }
     }
-    F::run(v, lds, tw);
+    F::run(v, lds, tw, threadIdx.x);
 #pragma unroll
     for (int i = 0; i < F::BPTO; ++i) {
         int c, b;
-        if (F::outer(i, c, b)) {
+        if (F::outer(threadIdx.x, i, c, b)) {
 #pragma unroll
             for (int j = 0; j < Cf::RO; ++j)
                 *reinterpret_cast<float2*>(s + (size_t)(b + j * Cf::SPAN) * nk + n0 + 2 * c) =
@@ -135,11 +135,11 @@ __global__ __launch_bounds__(LatCfg<N>::T) void k_lat_c2r(const float2* __restri
     }
 }
 
-template <int N>
-__global__ __launch_bounds__(LatCfg<N>::T) void k_lat_r2c(const float* __restrict__ r,
+template <int N, int C>
+__global__ __launch_bounds__((LatCfg<N, C>::T)) void k_lat_r2c(const float* __restrict__ r,
                                                           float2* __restrict__ rh, int nk,
                                                           const float2* __restrict__ tw, float scale) {
-    using Cf = LatCfg<N>;
+    using Cf = LatCfg<N, C>;
     using F = typename Cf::Fwd;
     extern __shared__ float2 lds[];
     const int n0 = xcd_tile(blockIdx.x, gridDim.x) * 2 * Cf::C;
@@ -147,24 +147,24 @@ __global__ __launch_bounds__(LatCfg<N>::T) void k_lat_r2c(const float* __restric
 #pragma unroll
     for (int i = 0; i < F::BPTO; ++i) {
         int c, b;
-        if (F::outer(i, c, b)) {
+        if (F::outer(threadIdx.x, i, c, b)) {
 #pragma unroll
             for (int j = 0; j < Cf::RO; ++j)
                 v[i * Cf::RO + j] =
                     *reinterpret_cast<const float2*>(r + (size_t)(b + j * Cf::SPAN) * nk + n0 + 2 * c);
         }
     }
-    F::run(v, lds, tw);
+    F::run(v, lds, tw, threadIdx.x);
     split_store<N, Cf::T, Cf::C>(lds, v, rh, nk, n0, scale);
 }
 
-template <int N>
-__global__ __launch_bounds__(LatCfg<N>::T) void k_lat_resid(const float2* __restrict__ zh,
+template <int N, int C>
+__global__ __launch_bounds__((LatCfg<N, C>::T)) void k_lat_resid(const float2* __restrict__ zh,
                                                             const float* __restrict__ y,
                                                             float2* __restrict__ rh, int nk,
                                                             const float2* __restrict__ tw, float scale,
                                                             float* __restrict__ partials) {
-    using Cf = LatCfg<N>;
+    using Cf = LatCfg<N, C>;
     using FI = typename Cf::Inv;
     using FF = typename Cf::Fwd;
     extern __shared__ float2 lds[];
@@ -173,18 +173,18 @@ __global__ __launch_bounds__(LatCfg<N>::T) void k_lat_resid(const float2* __rest
 #pragma unroll
     for (int i = 0; i < FI::BPTO; ++i) {
         int c, b;
-        if (FI::outer(i, c, b)) {
+        if (FI::outer(threadIdx.x, i, c, b)) {
 #pragma unroll
             for (int j = 0; j < Cf::RO; ++j)
                 v[i * Cf::RO + j] = hermitian_pair<N>(zh, nk, b + j * Cf::SPAN, n0 + 2 * c);
         }
     }
-    FI::run(v, lds, tw);
+    FI::run(v, lds, tw, threadIdx.x);
     float acc[1] = {0.f};
 #pragma unroll
     for (int i = 0; i < FI::BPTO; ++i) {
         int c, b;
-        if (FI::outer(i, c, b)) {
+        if (FI::outer(threadIdx.x, i, c, b)) {
 #pragma unroll
             for (int j = 0; j < Cf::RO; ++j) {
                 float2 s = cscale(v[i * Cf::RO + j], scale);
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(LatCfg<N>::T) void k_lat_resid(const float2* __rest
             }
         }
     }
-    FF::run(v, lds, tw);
+    FF::run(v, lds, tw, threadIdx.x);
     split_store<N, Cf::T, Cf::C>(lds, v, rh, nk, n0, scale);
     __syncthreads();
     block_sum_store<Cf::T, 1>(acc, reinterpret_cast<float*>(lds), partials + blockIdx.x * kRedSlots);
@@ -212,14 +212,14 @@ ISAM_DEV float2 soft_threshold(float2 u, float theta) {
     return cscale(u, f);
 }
 
-template <int N, bool NORMS>
-__global__ __launch_bounds__(LatCfg<N>::T) void k_lat_fista(float2* __restrict__ eta_hat,
+template <int N, int C, bool NORMS>
+__global__ __launch_bounds__((LatCfg<N, C>::T)) void k_lat_fista(float2* __restrict__ eta_hat,
                                                             const float2* __restrict__ ghat,
                                                             float2* __restrict__ z,
                                                             const float* __restrict__ w, int nk,
                                                             const float2* __restrict__ tw, float scale,
                                                             FistaStep fs, float* __restrict__ partials) {
-    using Cf = LatCfg<N>;
+    using Cf = LatCfg<N, C>;
     using FI = typename Cf::Inv;
     using FF = typename Cf::Fwd;
     constexpr int RO = Cf::RO, SPAN = Cf::SPAN;
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(LatCfg<N>::T) void k_lat_fista(float2* __restrict__
 #pragma unroll
     for (int i = 0; i < FI::BPTO; ++i) {
         int c, b;
-        if (FI::outer(i, c, b)) {
+        if (FI::outer(threadIdx.x, i, c, b)) {
 #pragma unroll
             for (int j = 0; j < RO; ++j) {
                 const size_t off = (size_t)(b + j * SPAN) * nk + m0 + c;
@@ -240,13 +240,13 @@ __global__ __launch_bounds__(LatCfg<N>::T) void k_lat_fista(float2* __restrict__
             }
         }
     }
-    FI::run(v, lds, tw);
-    if constexpr (NORMS) FI::run(gv, lds, tw);
+    FI::run(v, lds, tw, threadIdx.x);
+    if constexpr (NORMS) FI::run(gv, lds, tw, threadIdx.x);
     float acc[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int i = 0; i < FI::BPTO; ++i) {
         int c, b;
-        if (FI::outer(i, c, b)) {
+        if (FI::outer(threadIdx.x, i, c, b)) {
 #pragma unroll
             for (int j = 0; j < RO; ++j) {
                 const size_t off = (size_t)(b + j * SPAN) * nk + m0 + c;
@@ -267,11 +267,11 @@ __global__ __launch_bounds__(LatCfg<N>::T) void k_lat_fista(float2* __restrict__
             }
         }
     }
-    FF::run(v, lds, tw);
+    FF::run(v, lds, tw, threadIdx.x);
 #pragma unroll
     for (int i = 0; i < FF::BPTO; ++i) {
         int c, b;
-        if (FF::outer(i, c, b)) {
+        if (FF::outer(threadIdx.x, i, c, b)) {
 #pragma unroll
             for (int j = 0; j < RO; ++j)
                 eta_hat[(size_t)(b + j * SPAN) * nk + m0 + c] = cscale(v[i * RO + j], scale);
@@ -286,125 +286,115 @@ void set_lds(K kern, size_t bytes) {
     if (bytes > 65536) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <int N>
+template <int N, int C>
 hipError_t launch_c2c(const float2* in, float2* out, int nk, const float2* tw, int sign, hipStream_t s) {
-    using Cf = LatCfg<N>;
+    using Cf = LatCfg<N, C>;
     const float scale = 1.0f / sqrtf((float)N);
-    const dim3 grid(nk / Cf::C);
+    const dim3 grid(nk / C);
     if (sign < 0) {
-        set_lds(k_lat_c2c<N, -1>, Cf::LDS);
-        hipLaunchKernelGGL((k_lat_c2c<N, -1>), grid, dim3(Cf::T), Cf::LDS, s, in, out, nk, tw, scale);
+        set_lds(k_lat_c2c<N, C, -1>, Cf::LDS);
+        hipLaunchKernelGGL((k_lat_c2c<N, C, -1>), grid, dim3(Cf::T), Cf::LDS, s, in, out, nk, tw, scale);
     } else {
-        set_lds(k_lat_c2c<N, +1>, Cf::LDS);
-        hipLaunchKernelGGL((k_lat_c2c<N, +1>), grid, dim3(Cf::T), Cf::LDS, s, in, out, nk, tw, scale);
+        set_lds(k_lat_c2c<N, C, +1>, Cf::LDS);
+        hipLaunchKernelGGL((k_lat_c2c<N, C, +1>), grid, dim3(Cf::T), Cf::LDS, s, in, out, nk, tw, scale);
     }
     return hipGetLastError();
 }
 
-template <int N>
+template <int N, int C>
 hipError_t launch_c2r(const float2* zh, float* sout, int nk, const float2* tw, hipStream_t s) {
-    using Cf = LatCfg<N>;
-    set_lds(k_lat_c2r<N>, Cf::LDS);
-    hipLaunchKernelGGL(k_lat_c2r<N>, dim3(nk / (2 * Cf::C)), dim3(Cf::T), Cf::LDS, s, zh, sout, nk, tw,
+    using Cf = LatCfg<N, C>;
+    set_lds(k_lat_c2r<N, C>, Cf::LDS);
+    hipLaunchKernelGGL((k_lat_c2r<N, C>), dim3(nk / (2 * C)), dim3(Cf::T), Cf::LDS, s, zh, sout, nk, tw,
                        1.0f / sqrtf((float)N));
     return hipGetLastError();
 }
 
-template <int N>
+template <int N, int C>
 hipError_t launch_r2c(const float* r, float2* rh, int nk, const float2* tw, hipStream_t s) {
-    using Cf = LatCfg<N>;
-    set_lds(k_lat_r2c<N>, Cf::LDS);
-    hipLaunchKernelGGL(k_lat_r2c<N>, dim3(nk / (2 * Cf::C)), dim3(Cf::T), Cf::LDS, s, r, rh, nk, tw,
+    using Cf = LatCfg<N, C>;
+    set_lds(k_lat_r2c<N, C>, Cf::LDS);
+    hipLaunchKernelGGL((k_lat_r2c<N, C>), dim3(nk / (2 * C)), dim3(Cf::T), Cf::LDS, s, r, rh, nk, tw,
                        1.0f / sqrtf((float)N));
     return hipGetLastError();
 }
 
-template <int N>
+template <int N, int C>
 hipError_t launch_resid(const float2* zh, const float* y, float2* rh, int nk, const float2* tw,
                         float* partials, hipStream_t s) {
-    using Cf = LatCfg<N>;
-    set_lds(k_lat_resid<N>, Cf::LDS);
-    hipLaunchKernelGGL(k_lat_resid<N>, dim3(nk / (2 * Cf::C)), dim3(Cf::T), Cf::LDS, s, zh, y, rh, nk, tw,
+    using Cf = LatCfg<N, C>;
+    set_lds(k_lat_resid<N, C>, Cf::LDS);
+    hipLaunchKernelGGL((k_lat_resid<N, C>), dim3(nk / (2 * C)), dim3(Cf::T), Cf::LDS, s, zh, y, rh, nk, tw,
                        1.0f / sqrtf((float)N), partials);
     return hipGetLastError();
 }
 
-template <int N>
+template <int N, int C>
 hipError_t launch_fista(float2* eh, const float2* gh, float2* z, const float* w, int nk, const float2* tw,
                         FistaStep fs, float* partials, hipStream_t s) {
-    using Cf = LatCfg<N>;
-    const dim3 grid(nk / Cf::C);
+    using Cf = LatCfg<N, C>;
+    const dim3 grid(nk / C);
     const float scale = 1.0f / sqrtf((float)N);
     if (fs.norms) {
-        set_lds(k_lat_fista<N, true>, Cf::LDS);
-        hipLaunchKernelGGL((k_lat_fista<N, true>), grid, dim3(Cf::T), Cf::LDS, s, eh, gh, z, w, nk, tw, scale,
-                           fs, partials);
+        set_lds(k_lat_fista<N, C, true>, Cf::LDS);
+        hipLaunchKernelGGL((k_lat_fista<N, C, true>), grid, dim3(Cf::T), Cf::LDS, s, eh, gh, z, w, nk, tw,
+                           scale, fs, partials);
     } else {
-        set_lds(k_lat_fista<N, false>, Cf::LDS);
-        hipLaunchKernelGGL((k_lat_fista<N, false>), grid, dim3(Cf::T), Cf::LDS, s, eh, gh, z, w, nk, tw, scale,
-                           fs, partials);
+        set_lds(k_lat_fista<N, C, false>, Cf::LDS);
+        hipLaunchKernelGGL((k_lat_fista<N, C, false>), grid, dim3(Cf::T), Cf::LDS, s, eh, gh, z, w, nk, tw,
+                           scale, fs, partials);
     }
     return hipGetLastError();
 }
 
-template <int N>
-int blocks_of(int nk, int kind) {
-    using Cf = LatCfg<N>;
-    return kind == 0 ? nk / Cf::C : nk / (2 * Cf::C);
-}
-
 }  // namespace
 
-#define ISAM_LAT_SWITCH(N_, CALL)          \
-    switch (N_) {                          \
-        case 1: { constexpr int N = 1; CALL; } \
-        case 2: { constexpr int N = 2; CALL; } \
-        case 4: { constexpr int N = 4; CALL; } \
-        case 8: { constexpr int N = 8; CALL; } \
-        case 16: { constexpr int N = 16; CALL; } \
-        case 32: { constexpr int N = 32; CALL; } \
-        case 64: { constexpr int N = 64; CALL; } \
-        case 128: { constexpr int N = 128; CALL; } \
-        case 256: { constexpr int N = 256; CALL; } \
-        case 512: { constexpr int N = 512; CALL; } \
-        case 1024: { constexpr int N = 1024; CALL; } \
-        case 2048: { constexpr int N = 2048; CALL; } \
-        default: return hipErrorInvalidValue; \
+// Tile widths built per lateral length: C complex lanes per tile (2C real columns for the
+// real transforms).  Small transforms use 8 lanes; from 256 A-scans up the plan picks one
+// of {2, 4, 8} (tunable; 4 by default: 32-byte row segments, twice the workgroups of 8).
+#define ISAM_LAT_C(CALL)                                               \
+    switch (p->lat_c) {                                                \
+        case 2: { constexpr int C = 2; CALL; }                         \
+        case 8: { constexpr int C = N >= 2048 ? 4 : 8; CALL; }         \
+        default: { constexpr int C = 4; CALL; }                        \
+    }
+#define ISAM_LAT_SWITCH(CALL)                                          \
+    switch (p->nx) {                                                   \
+        case 1: { constexpr int N = 1, C = 8; CALL; }                  \
+        case 2: { constexpr int N = 2, C = 8; CALL; }                  \
+        case 4: { constexpr int N = 4, C = 8; CALL; }                  \
+        case 8: { constexpr int N = 8, C = 8; CALL; }                  \
+        case 16: { constexpr int N = 16, C = 8; CALL; }                \
+        case 32: { constexpr int N = 32, C = 8; CALL; }                \
+        case 64: { constexpr int N = 64, C = 8; CALL; }                \
+        case 128: { constexpr int N = 128, C = 8; CALL; }              \
+        case 256: { constexpr int N = 256; ISAM_LAT_C(CALL) }          \
+        case 512: { constexpr int N = 512; ISAM_LAT_C(CALL) }          \
+        case 1024: { constexpr int N = 1024; ISAM_LAT_C(CALL) }        \
+        case 2048: { constexpr int N = 2048; ISAM_LAT_C(CALL) }        \
+        default: return hipErrorInvalidValue;                          \
     }
 
 hipError_t lat_c2c(const isam_plan_s* p, const float2* in, float2* out, int sign, hipStream_t s) {
-    ISAM_LAT_SWITCH(p->nx, return launch_c2c<N>(in, out, p->nk, p->twX, sign, s));
+    ISAM_LAT_SWITCH(return (launch_c2c<N, C>(in, out, p->nk, p->twX, sign, s)));
 }
 hipError_t lat_c2r(const isam_plan_s* p, const float2* zh, float* sout, hipStream_t s) {
-    ISAM_LAT_SWITCH(p->nx, return launch_c2r<N>(zh, sout, p->nk, p->twX, s));
+    ISAM_LAT_SWITCH(return (launch_c2r<N, C>(zh, sout, p->nk, p->twX, s)));
 }
 hipError_t lat_r2c(const isam_plan_s* p, const float* r, float2* rh, hipStream_t s) {
-    ISAM_LAT_SWITCH(p->nx, return launch_r2c<N>(r, rh, p->nk, p->twX, s));
+    ISAM_LAT_SWITCH(return (launch_r2c<N, C>(r, rh, p->nk, p->twX, s)));
 }
 hipError_t lat_resid(const isam_plan_s* p, const float2* zh, const float* y, float2* rh, float* partials,
                      hipStream_t s) {
-    ISAM_LAT_SWITCH(p->nx, return launch_resid<N>(zh, y, rh, p->nk, p->twX, partials, s));
+    ISAM_LAT_SWITCH(return (launch_resid<N, C>(zh, y, rh, p->nk, p->twX, partials, s)));
 }
 hipError_t lat_fista(const isam_plan_s* p, float2* eh, const float2* gh, float2* z, const float* w,
                      FistaStep fs, float* partials, hipStream_t s) {
-    ISAM_LAT_SWITCH(p->nx, return launch_fista<N>(eh, gh, z, w, p->nk, p->twX, fs, partials, s));
+    ISAM_LAT_SWITCH(return (launch_fista<N, C>(eh, gh, z, w, p->nk, p->twX, fs, partials, s)));
 }
 int lat_blocks(const isam_plan_s* p, int kind) {
-    switch (p->nx) {
-        case 1: return blocks_of<1>(p->nk, kind);
-        case 2: return blocks_of<2>(p->nk, kind);
-        case 4: return blocks_of<4>(p->nk, kind);
-        case 8: return blocks_of<8>(p->nk, kind);
-        case 16: return blocks_of<16>(p->nk, kind);
-        case 32: return blocks_of<32>(p->nk, kind);
-        case 64: return blocks_of<64>(p->nk, kind);
-        case 128: return blocks_of<128>(p->nk, kind);
-        case 256: return blocks_of<256>(p->nk, kind);
-        case 512: return blocks_of<512>(p->nk, kind);
-        case 1024: return blocks_of<1024>(p->nk, kind);
-        case 2048: return blocks_of<2048>(p->nk, kind);
-        default: return 0;
-    }
+    auto f = [&](int C) { return kind == 0 ? p->nk / C : p->nk / (2 * C); };
+    ISAM_LAT_SWITCH(return f(C));
 }
 
 }  // namespace isam

@@ -15,10 +15,9 @@
 // l = nx/2) and writes the Hermitian half Z[l] = (X[l] + conj X[nx - l]) / 2, which the
 // C2R lateral pass turns into Re(F^{-1} X) (Eq. 5).
 //
-// Adjoint: the exact transpose.  The interpolation transpose is a gather: for each
-// oversampled cell the contributing (n, j) are found from a per-column map, built in
-// LDS, of the first sample reaching each unwrapped cell; t_n increases with n by at
-// least 2 per sample, so each cell has about J/2 contributors and no atomics are needed.
+// Adjoint: the exact transpose, one column per workgroup.  The transposed interpolation
+// is formed without atomics (see k_nufft_adj): t_n increases by at least 2 per sample,
+// so the contributions to a cell can be given fixed, single-writer slots.
 #include <algorithm>
 
 #include "common.hpp"
@@ -28,25 +27,41 @@
 namespace isam {
 namespace {
 
-constexpr int kGsentinel = -(1 << 30);
-
 template <int K>
 struct NuCfg {
     static constexpr int NK = K / 2;
     static constexpr int P = ilog2(K);
     static constexpr int RO = 1 << fft_radix_log(P, 0);
     static constexpr int NB = K / RO;
-    static constexpr int T = NB < 64 ? 64 : (NB > 256 ? 256 : NB);
+    static constexpr int T = NB < 64 ? 64 : (NB > 256 ? 256 : NB);    // threads per column
     static constexpr int NPT = (NK + T - 1) / T;           // output samples per thread
     static constexpr int SPAN = K / RO;
-    static constexpr int LOMAX = 2 * K;                    // unwrapped cells of one column
     using Fwd = LdsFft<K, 1, T, +1>;
-    using Adj = LdsFft<K, 1, T, -1>;
-    static constexpr size_t LDS_FWD = (size_t)(K + kWtabEntries) * sizeof(float2);
-    static constexpr size_t AUX = (size_t)NK * (sizeof(float2) + sizeof(int) + sizeof(float)) +
-                                  (size_t)LOMAX * sizeof(unsigned short);
-    static constexpr size_t REGION = AUX > K * sizeof(float2) ? AUX : K * sizeof(float2);
-    static constexpr size_t LDS_ADJ = (size_t)kWtabEntries * sizeof(float2) + REGION;
+    // padded FFT buffer (float2), also holding Y with its J-entry wrap halo
+    static constexpr int BUF = lds_size(K) > K + 8 ? lds_size(K) : K + 8;
+    // forward: two columns in parallel (two halves of the block), shared weight table
+    static constexpr size_t LDS_FWD = (size_t)(2 * BUF + kWtabEntries) * sizeof(float2);
+};
+
+// Adjoint: one column per block, radix-8 passes so that K/8 threads share the column.
+// Samples are processed in chunks of CS; a chunk's cells fit SLOTC slots-triples.
+template <int K>
+struct NuAdjCfg {
+    static constexpr int NK = K / 2;
+    static constexpr int P = ilog2(K);
+    static constexpr int L = 3;
+    static constexpr int RO = 1 << fft_radix_log(P, 0, L);
+    static constexpr int NB = K / RO;
+    static constexpr int T = NB < 64 ? 64 : (NB > 512 ? 512 : NB);
+    static constexpr int SPAN = K / RO;
+    static constexpr int CS = T < NK / 4 ? T : NK / 4;            // samples per chunk
+    static constexpr int NCH = NK / CS;                             // chunks
+    static constexpr int SLOTC = 2 * CS + CS / 8 + 16;             // cells of one chunk
+    using Adj = LdsFft<K, 1, T, -1, 1, L>;
+    static constexpr size_t YBUF = (size_t)lds_size(K) * sizeof(float2);
+    static constexpr size_t SLOTS = (size_t)3 * SLOTC * sizeof(float2);
+    static constexpr size_t LDS = (size_t)kWtabEntries * sizeof(float2) + YBUF + SLOTS;
+    static_assert(SLOTC < K, "a chunk's cells map to distinct oversampled cells");
 };
 
 // Stolt grid position of sample n of a column with q^2 = q2 (FP64).  Returns false on an
@@ -91,14 +106,14 @@ ISAM_DEV float2 modulation(const NufftArgs& a, float Bl, int n, double t) {
 
 template <int K>
 ISAM_DEV void forward_column(const NufftArgs& a, const float2* __restrict__ src, int col, float2* buf,
-                             const float2* wt, float2 (&xt)[NuCfg<K>::NPT]) {
+                             const float2* wt, float2 (&xt)[NuCfg<K>::NPT], int tid) {
     using Cf = NuCfg<K>;
     using F = typename Cf::Fwd;
     float2 v[F::EPT];
 #pragma unroll
     for (int i = 0; i < F::BPTO; ++i) {
         int c, b;
-        if (F::outer(i, c, b)) {
+        if (F::outer(tid, i, c, b)) {
 #pragma unroll
             for (int j = 0; j < Cf::RO; ++j) {
                 const int x = b + j * Cf::SPAN;
@@ -107,14 +122,19 @@ ISAM_DEV void forward_column(const NufftArgs& a, const float2* __restrict__ src,
             }
         }
     }
-    F::run(v, buf, a.tw);
+    F::run(v, buf, a.tw, tid);
     __syncthreads();
+    // Y in natural order, plus a halo Y[K + i] = Y[i] so the J taps of a sample are contiguous
 #pragma unroll
     for (int i = 0; i < F::BPTO; ++i) {
         int c, b;
-        if (F::outer(i, c, b)) {
+        if (F::outer(tid, i, c, b)) {
 #pragma unroll
-            for (int j = 0; j < Cf::RO; ++j) buf[b + j * Cf::SPAN] = v[i * Cf::RO + j];
+            for (int j = 0; j < Cf::RO; ++j) {
+                const int x = b + j * Cf::SPAN;
+                buf[x] = v[i * Cf::RO + j];
+                if (j == 0 && x < kJ) buf[K + x] = v[i * Cf::RO + j];
+            }
         }
     }
     __syncthreads();
@@ -122,124 +142,160 @@ ISAM_DEV void forward_column(const NufftArgs& a, const float2* __restrict__ src,
     const float Bl = a.Bl[col];
 #pragma unroll
     for (int r = 0; r < Cf::NPT; ++r) {
-        const int n = threadIdx.x + r * Cf::T;
+        const int n = tid + r * Cf::T;
         float2 out = c2(0.f, 0.f);
         double t;
         int fl;
         float tau;
         if (n < a.nk && stolt_point(a, q2, n, t, fl, tau)) {
-            const int base = fl - kJ / 2 + 1;                       // tap j = 1 at g0 + 1
+            const float2* y = buf + ((fl - kJ / 2 + 1) & (K - 1));   // tap j = 1 at g0 + 1
             float2 acc = c2(0.f, 0.f);
 #pragma unroll
-            for (int jj = 0; jj < kJ; ++jj)
-                acc = cfma(weight(wt, tau, jj), buf[(base + jj) & (K - 1)], acc);
+            for (int jj = 0; jj < kJ; ++jj) acc = cfma(weight(wt, tau, jj), y[jj], acc);
             out = cmul(acc, modulation(a, Bl, n, t));
         }
         xt[r] = out;
     }
 }
 
+// Block = two halves of T threads; half h transforms one column of the lateral pair
+// (l, nx - l) (block 0: the self-paired l = 0 and l = nx/2), then half 0 writes the
+// Hermitian combination.
 template <int K>
-__global__ __launch_bounds__(NuCfg<K>::T) void k_nufft_fwd(const float2* __restrict__ etahat,
-                                                           float2* __restrict__ zh, NufftArgs a) {
+__global__ __launch_bounds__(2 * NuCfg<K>::T) void k_nufft_fwd(const float2* __restrict__ etahat,
+                                                               float2* __restrict__ zh, NufftArgs a) {
     using Cf = NuCfg<K>;
     extern __shared__ float2 smem[];
-    float2* buf = smem;
-    float2* wt = smem + K;
-    for (int i = threadIdx.x; i < kWtabEntries; i += Cf::T) wt[i] = a.wtab[i];
+    const int half = threadIdx.x / Cf::T, tid = threadIdx.x % Cf::T;
+    float2* buf = smem + half * Cf::BUF;
+    float2* wt = smem + 2 * Cf::BUF;
+    for (int i = threadIdx.x; i < kWtabEntries; i += 2 * Cf::T) wt[i] = a.wtab[i];
     const int b = blockIdx.x;
-    const int colA = b == 0 ? 0 : b;
+    const int colA = b;
     const int colB = b == 0 ? (a.nx >= 2 ? a.nx / 2 : -1) : a.nx - b;
-    float2 xa[Cf::NPT], xb[Cf::NPT];
-    forward_column<K>(a, etahat + (size_t)colA * a.nk, colA, buf, wt, xa);
-    if (colB >= 0) forward_column<K>(a, etahat + (size_t)colB * a.nk, colB, buf, wt, xb);
+    const int col = half == 0 ? colA : (colB >= 0 ? colB : colA);
+    float2 xt[Cf::NPT];
+    forward_column<K>(a, etahat + (size_t)col * a.nk, col, buf, wt, xt, tid);
+    __syncthreads();
+    if (half == 1) {
 #pragma unroll
-    for (int r = 0; r < Cf::NPT; ++r) {
-        const int n = threadIdx.x + r * Cf::T;
-        if (n >= a.nk) continue;
-        if (b == 0) {
-            zh[n] = c2(xa[r].x, 0.f);
-            if (colB >= 0) zh[(size_t)colB * a.nk + n] = c2(xb[r].x, 0.f);
-        } else {
-            zh[(size_t)b * a.nk + n] = cscale(cadd(xa[r], cconj(xb[r])), 0.5f);
+        for (int r = 0; r < Cf::NPT; ++r) {
+            const int n = tid + r * Cf::T;
+            if (n < a.nk) buf[n] = xt[r];
+        }
+    }
+    __syncthreads();
+    if (half == 0) {
+        const float2* other = smem + Cf::BUF;
+#pragma unroll
+        for (int r = 0; r < Cf::NPT; ++r) {
+            const int n = tid + r * Cf::T;
+            if (n >= a.nk) continue;
+            const float2 xb = other[n];
+            if (b == 0) {
+                zh[n] = c2(xt[r].x, 0.f);
+                if (colB >= 0) zh[(size_t)colB * a.nk + n] = c2(xb.x, 0.f);
+            } else {
+                zh[(size_t)b * a.nk + n] = cscale(cadd(xt[r], cconj(xb)), 0.5f);
+            }
         }
     }
 }
 
+// Transposed NUFFT of one column per block.  Column l reads the half-spectrum row
+// min(l, nx - l) of the real residual's lateral transform (conjugated above nx/2).
+//
+// The transposed interpolation Y'[g] = sum over (n, j) with g0_n + j = g of
+// conj(u_j(tau_n)) V_n is formed chunk by chunk without atomics: within a chunk every
+// sample n writes its J products into a slot triple of its target cells, slot j / 2 of
+// cell g0_n + 1 + j.  Two samples that reach one cell differ in g0 by at least 2, so they
+// never share a slot: each slot has one writer.  Each cell then sums its three slots (in
+// slot order) into Y'[cell mod K]; chunks follow one another, so every sum is formed in a
+// fixed order and the result is bitwise repeatable.
 template <int K>
-ISAM_DEV void adjoint_column(const NufftArgs& a, const float2* __restrict__ rh, int rrow, bool conj_in,
-                             int col, float2* region, const float2* wt, float2* __restrict__ dst,
-                             int* s_nev) {
-    using Cf = NuCfg<K>;
+__global__ __launch_bounds__(NuAdjCfg<K>::T) void k_nufft_adj(const float2* __restrict__ rh,
+                                                              float2* __restrict__ ghat, NufftArgs a) {
+    using Cf = NuAdjCfg<K>;
     using F = typename Cf::Adj;
-    float2* V = region;
-    int* G = reinterpret_cast<int*>(V + Cf::NK);
-    float* TAU = reinterpret_cast<float*>(G + Cf::NK);
-    unsigned short* LO = reinterpret_cast<unsigned short*>(TAU + Cf::NK);
-    if (threadIdx.x == 0) *s_nev = a.nk;
-    __syncthreads();
+    constexpr int T = Cf::T;
+    extern __shared__ float2 smem[];
+    __shared__ int s_red[T / 64];
+    float2* wt = smem;
+    float2* Y = smem + kWtabEntries;                                  // Y'[g], then the FFT tile
+    float2* SL = reinterpret_cast<float2*>(reinterpret_cast<char*>(Y) + Cf::YBUF);   // [SLOTC][3]
+    const int tid = threadIdx.x;
+    const int col = blockIdx.x;
+    const int row = col <= a.nx / 2 ? col : a.nx - col;
+    const bool conj_in = col > a.nx / 2;
+    for (int i = tid; i < kWtabEntries; i += T) wt[i] = a.wtab[i];
+    for (int i = tid; i < K; i += T) Y[i] = c2(0.f, 0.f);
     const double q2 = a.q2[col];
     const float Bl = a.Bl[col];
-    // phase A: Stolt points and modulated residual of every sample
-#pragma unroll
-    for (int r = 0; r < Cf::NPT; ++r) {
-        const int n = threadIdx.x + r * Cf::T;
-        if (n >= a.nk) continue;
+    for (int ch = 0; ch < Cf::NCH; ++ch) {
+        const int n = ch * Cf::CS + tid;
+        const bool mine = tid < Cf::CS;
         double t;
-        int fl;
-        float tau;
-        if (stolt_point(a, q2, n, t, fl, tau)) {
-            float2 x = rh[(size_t)rrow * a.nk + n];
+        int fl = 0;
+        float tau = 0.f;
+        const bool prop = mine && stolt_point(a, q2, n, t, fl, tau);
+        float2 vn = c2(0.f, 0.f);
+        if (prop) {
+            float2 x = rh[(size_t)row * a.nk + n];
             if (conj_in) x = cconj(x);
-            V[n] = cmulc(x, modulation(a, Bl, n, t));
-            G[n] = fl - kJ / 2;
-            TAU[n] = tau;
-            atomicMin(s_nev, n);
-        } else {
-            V[n] = c2(0.f, 0.f);
-            G[n] = kGsentinel;
-            TAU[n] = 0.f;
+            vn = cmulc(x, modulation(a, Bl, n, t));
         }
-    }
-    __syncthreads();
-    const int nev = *s_nev;
-    float2 v[F::EPT];
-    if (nev < a.nk) {
-        const int base = G[nev] + 1;
-        const int top = G[a.nk - 1] + kJ;
-        // phase B: first contributing sample of every unwrapped cell in [base, top]
-        for (int n = nev + threadIdx.x; n < a.nk; n += Cf::T) {
-            const int from = n == nev ? base : G[n - 1] + kJ + 1;
-            const int to = G[n] + kJ;
-            for (int c = from; c <= to; ++c) LO[c - base] = (unsigned short)n;
-        }
+        // chunk base: smallest g0 among its propagating samples (g0 grows with n)
+        int g0 = prop ? fl - kJ / 2 : 0x7fffffff;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) g0 = min(g0, __shfl_xor(g0, off, 64));
+        if ((tid & 63) == 0) s_red[tid >> 6] = g0;
+        for (int i = tid; i < 3 * Cf::SLOTC; i += T) SL[i] = c2(0.f, 0.f);
         __syncthreads();
-        // phase C: gather into the cells this thread feeds to the FFT's first pass
+        int cbase = s_red[0];
 #pragma unroll
-        for (int i = 0; i < F::BPTO; ++i) {
-            int cc, b;
-            if (F::outer(i, cc, b)) {
+        for (int w = 1; w < T / 64; ++w) cbase = min(cbase, s_red[w]);
+        const bool any = cbase != 0x7fffffff;
+        if (prop) {
+            // cell g0 + 1 + j (relative to cbase + 1), slot j / 2
+            float2* dst = SL + 3 * (fl - kJ / 2 - cbase);
+            const float tp = tau * kPieces;
+            const int p = min((int)tp, kPieces - 1);
+            const float xl = tp - (float)p;
+            const float4* rowp = reinterpret_cast<const float4*>(wt + p * kJ * 4);
 #pragma unroll
-                for (int j = 0; j < Cf::RO; ++j) {
-                    const int g = b + j * Cf::SPAN;
-                    float2 acc = c2(0.f, 0.f);
-                    for (int cell = base + ((g - base) & (K - 1)); cell <= top; cell += K) {
-                        for (int n = LO[cell - base]; n < a.nk && G[n] + 1 <= cell; ++n)
-                            acc = cfmac(weight(wt, TAU[n], cell - G[n] - 1), V[n], acc);
-                    }
-                    v[i * Cf::RO + j] = acc;
-                }
+            for (int jj = 0; jj < kJ; ++jj) {
+                const float4 ca = rowp[2 * jj], cb = rowp[2 * jj + 1];
+                float2 w;
+                w.x = fmaf(fmaf(fmaf(cb.z, xl, cb.x), xl, ca.z), xl, ca.x);
+                w.y = fmaf(fmaf(fmaf(cb.w, xl, cb.y), xl, ca.w), xl, ca.y);
+                dst[3 * jj + (jj >> 1)] = cfmac(w, vn, c2(0.f, 0.f));
             }
         }
-    } else {
-#pragma unroll
-        for (int i = 0; i < F::EPT; ++i) v[i] = c2(0.f, 0.f);
+        __syncthreads();
+        if (any) {
+            for (int c = tid; c < Cf::SLOTC; c += T) {
+                const float2 s0 = SL[3 * c], s1 = SL[3 * c + 1], s2 = SL[3 * c + 2];
+                const int g = (cbase + 1 + c) & (K - 1);
+                Y[g] = cadd(Y[g], cadd(cadd(s0, s1), s2));
+            }
+        }
+        __syncthreads();
     }
-    F::run(v, region, a.tw);        // opens with a barrier: phase C reads of the region are done
+    float2 v[F::EPT];
 #pragma unroll
     for (int i = 0; i < F::BPTO; ++i) {
         int cc, b;
-        if (F::outer(i, cc, b)) {
+        if (F::outer(tid, i, cc, b)) {
+#pragma unroll
+            for (int j = 0; j < Cf::RO; ++j) v[i * Cf::RO + j] = Y[b + j * Cf::SPAN];
+        }
+    }
+    F::run(v, Y, a.tw8, tid);         // opens with a barrier: the reads of Y above are done
+    float2* dst = ghat + (size_t)col * a.nk;
+#pragma unroll
+    for (int i = 0; i < F::BPTO; ++i) {
+        int cc, b;
+        if (F::outer(tid, i, cc, b)) {
 #pragma unroll
             for (int j = 0; j < Cf::RO; ++j) {
                 const int x = b + j * Cf::SPAN;
@@ -247,29 +303,6 @@ ISAM_DEV void adjoint_column(const NufftArgs& a, const float2* __restrict__ rh, 
                 if (u < a.nk) dst[u] = cscale(v[i * Cf::RO + j], a.sm[u]);
             }
         }
-    }
-    __syncthreads();
-}
-
-template <int K>
-__global__ __launch_bounds__(NuCfg<K>::T) void k_nufft_adj(const float2* __restrict__ rh,
-                                                           float2* __restrict__ ghat, NufftArgs a) {
-    using Cf = NuCfg<K>;
-    extern __shared__ float2 smem[];
-    __shared__ int s_nev;
-    float2* wt = smem;
-    float2* region = smem + kWtabEntries;
-    for (int i = threadIdx.x; i < kWtabEntries; i += Cf::T) wt[i] = a.wtab[i];
-    const int b = blockIdx.x;
-    if (b == 0) {
-        adjoint_column<K>(a, rh, 0, false, 0, region, wt, ghat, &s_nev);
-        if (a.nx >= 2) {
-            const int ny = a.nx / 2;
-            adjoint_column<K>(a, rh, ny, false, ny, region, wt, ghat + (size_t)ny * a.nk, &s_nev);
-        }
-    } else {
-        adjoint_column<K>(a, rh, b, false, b, region, wt, ghat + (size_t)b * a.nk, &s_nev);
-        adjoint_column<K>(a, rh, b, true, a.nx - b, region, wt, ghat + (size_t)(a.nx - b) * a.nk, &s_nev);
     }
 }
 
@@ -283,17 +316,16 @@ template <int K>
 hipError_t launch_fwd(const isam_plan_s* p, const float2* etahat, float2* zh, hipStream_t s) {
     using Cf = NuCfg<K>;
     set_lds(k_nufft_fwd<K>, Cf::LDS_FWD);
-    hipLaunchKernelGGL(k_nufft_fwd<K>, dim3(std::max(1, p->nx / 2)), dim3(Cf::T), Cf::LDS_FWD, s, etahat, zh,
-                       p->nufft_args());
+    hipLaunchKernelGGL(k_nufft_fwd<K>, dim3(std::max(1, p->nx / 2)), dim3(2 * Cf::T), Cf::LDS_FWD, s, etahat,
+                       zh, p->nufft_args());
     return hipGetLastError();
 }
 
 template <int K>
 hipError_t launch_adj(const isam_plan_s* p, const float2* rh, float2* ghat, hipStream_t s) {
-    using Cf = NuCfg<K>;
-    set_lds(k_nufft_adj<K>, Cf::LDS_ADJ);
-    hipLaunchKernelGGL(k_nufft_adj<K>, dim3(std::max(1, p->nx / 2)), dim3(Cf::T), Cf::LDS_ADJ, s, rh, ghat,
-                       p->nufft_args());
+    using Cf = NuAdjCfg<K>;
+    set_lds(k_nufft_adj<K>, Cf::LDS);
+    hipLaunchKernelGGL(k_nufft_adj<K>, dim3(p->nx), dim3(Cf::T), Cf::LDS, s, rh, ghat, p->nufft_args());
     return hipGetLastError();
 }
 
@@ -313,6 +345,20 @@ hipError_t launch_adj(const isam_plan_s* p, const float2* rh, float2* ghat, hipS
         default: return hipErrorInvalidValue;       \
     }
 
+#define ISAM_K_SWITCH_INT(K_, CALL)                 \
+    switch (K_) {                                   \
+        case 32: { constexpr int K = 32; CALL; break; }    \
+        case 64: { constexpr int K = 64; CALL; break; }    \
+        case 128: { constexpr int K = 128; CALL; break; }  \
+        case 256: { constexpr int K = 256; CALL; break; }  \
+        case 512: { constexpr int K = 512; CALL; break; }  \
+        case 1024: { constexpr int K = 1024; CALL; break; } \
+        case 2048: { constexpr int K = 2048; CALL; break; } \
+        case 4096: { constexpr int K = 4096; CALL; break; } \
+        case 8192: { constexpr int K = 8192; CALL; break; } \
+        default: return 0;                          \
+    }
+
 hipError_t nufft_fwd(const isam_plan_s* p, const float2* etahat, float2* zh, hipStream_t s) {
     ISAM_K_SWITCH(p->K, return launch_fwd<K>(p, etahat, zh, s));
 }
@@ -321,30 +367,39 @@ hipError_t nufft_adj(const isam_plan_s* p, const float2* rh, float2* ghat, hipSt
     ISAM_K_SWITCH(p->K, return launch_adj<K>(p, rh, ghat, s));
 }
 
-// Host replica of the Stolt span per column: the unwrapped cells [G_first + 1, G_last + J]
-// must fit the LDS map of 2K entries (a margin of a few cells covers FP64 rounding
-// differences between host and device at floor boundaries).
+// Host replica of the Stolt positions per column.  Two bounds keep the adjoint exact:
+// (1) consecutive propagating samples advance by at least 2 cells (dkz/dk >= 2 holds for
+// any propagating component), so no two samples share a slot of a cell; (2) the cells of a
+// chunk of samples, [g0_first + 1, g0_last + J], fit the chunk's slot array.  A margin of
+// a few cells covers FP64 rounding differences between host and device at floor boundaries.
 int nufft_span_ok(const isam_plan_s* p) {
+    int cs = 64;
+    int slotc = 0;
+    ISAM_K_SWITCH_INT(p->K, cs = NuAdjCfg<K>::CS; slotc = NuAdjCfg<K>::SLOTC);
     for (int i = 0; i < p->nx; ++i) {
         const int l = (i < (p->nx + 1) / 2) ? i : i - p->nx;
         const double q = 2.0 * 3.14159265358979323846 * l / (p->nx * p->g.dx);
         const double q2 = q * q;
-        int first = -1;
-        for (int n = 0; n < p->nk; ++n) {
+        auto g0 = [&](int n, bool& prop) {
             const double k = p->kc + (double)(n - p->nk / 2) * p->dk;
-            if (4.0 * k * k - q2 > 0.0) {
-                first = n;
-                break;
-            }
-        }
-        if (first < 0) continue;
-        auto tpos = [&](int n) {
-            const double k = p->kc + (double)(n - p->nk / 2) * p->dk;
-            return std::floor(std::sqrt(4.0 * k * k - q2) * p->cT);
+            const double d = 4.0 * k * k - q2;
+            prop = d > 0.0;
+            return prop ? std::floor(std::sqrt(d) * p->cT) - kJ / 2 : 0.0;
         };
-        const double span = tpos(p->nk - 1) - tpos(first) + kJ;
-        if (span + 4 > 2.0 * p->K) return 0;
-        if (p->nk > 65535) return 0;
+        for (int c0 = 0; c0 < p->nk; c0 += cs) {
+            double first = 0, last = 0, prev = 0;
+            bool have = false;
+            for (int n = c0; n < c0 + cs && n < p->nk; ++n) {
+                bool prop;
+                const double g = g0(n, prop);
+                if (!prop) continue;
+                if (have && g - prev < 2.0) return 0;
+                if (!have) first = g;
+                have = true;
+                prev = last = g;
+            }
+            if (have && last - first + kJ + 4 > slotc) return 0;
+        }
     }
     return 1;
 }

@@ -25,7 +25,8 @@ struct NufftArgs {
     const float2* En;       // [nk] e^{i phi(k_n)} e^{2 i k_n z_f} / sqrt(nz)
     const float* sm;        // [nk] Kaiser-Bessel scaling at depth index i = m + nz/2
     const float2* wtab;     // [kPieces][kJ][4] cubic coefficients of the weights (focus-phased)
-    const float2* tw;       // [K] exp(-2 pi i e / K)
+    const float2* tw;       // staged twiddles of the K-point FFT, radices up to 16
+    const float2* tw8;      // staged twiddles of the K-point FFT, radices up to 8
 };
 
 struct Reduce {
@@ -43,6 +44,7 @@ struct isam_plan_s {
     double kc, band, dk, dz, cT, beta, mf;
     int mi;
     double mr;
+    int lat_c = 0;                // lateral tile width (complex lanes); 0 = default for nx
 
     // tables (device)
     double* q2 = nullptr;
@@ -51,6 +53,7 @@ struct isam_plan_s {
     float* sm = nullptr;
     float2* wtab = nullptr;
     float2* twK = nullptr;
+    float2* twK8 = nullptr;
     float2* twX = nullptr;
     double* wscratch = nullptr;   // FP64 scratch of the weight-table build
 
@@ -64,6 +67,16 @@ struct isam_plan_s {
     float* sbuf = nullptr;        // [nx][nk] real spectra scratch
     isam::Reduce red;
     double* host_sums = nullptr;  // pinned host copy of red.sums
+
+    // per-pass timing (isam_timing)
+    int timing_on = 0;
+    int tev_used = 0;
+    int tev_cap = 0;
+    hipEvent_t* tev = nullptr;    // event pairs
+    int* ttag = nullptr;          // pass of each pair
+    hipStream_t tstream = nullptr;
+    double tms[ISAM_NPASS] = {};
+    int64_t tcnt[ISAM_NPASS] = {};
 
     isam::NufftArgs nufft_args() const;
 };

@@ -9,6 +9,7 @@
 //                frequency, so an iteration is four passes.
 #include <algorithm>
 #include <cmath>
+#include <new>
 
 #include "common.hpp"
 #include "plan.hpp"
@@ -19,17 +20,27 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 
-// FP64 sums of the per-workgroup partials, one thread per slot (fixed order: deterministic).
-__global__ void k_finalize(const float* __restrict__ partials, int nblocks, int nslots,
-                           double* __restrict__ sums, int mode_max) {
-    const int s = threadIdx.x;
-    if (s >= nslots) return;
-    double acc = 0.0;
-    for (int b = 0; b < nblocks; ++b) {
-        const double v = partials[b * kRedSlots + s];
-        acc = mode_max ? fmax(acc, v) : acc + v;
+// FP64 sums (or maxima) of the per-workgroup partials: strided per-thread sums, then a
+// fixed-order tree, so the result does not depend on scheduling.
+__global__ __launch_bounds__(256) void k_finalize(const float* __restrict__ partials, int nblocks,
+                                                  int nslots, double* __restrict__ sums, int mode_max) {
+    __shared__ double sh[256];
+    const int tid = threadIdx.x;
+    for (int s = 0; s < nslots; ++s) {
+        double acc = 0.0;
+        for (int b = tid; b < nblocks; b += 256) {
+            const double v = partials[b * kRedSlots + s];
+            acc = mode_max ? fmax(acc, v) : acc + v;
+        }
+        sh[tid] = acc;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (tid < w) sh[tid] = mode_max ? fmax(sh[tid], sh[tid + w]) : sh[tid] + sh[tid + w];
+            __syncthreads();
+        }
+        if (tid == 0) sums[s] = sh[0];
+        __syncthreads();
     }
-    sums[s] = acc;
 }
 
 // Partial sum of |x|^2 (slot 0) over a complex vector; 256 threads per block.
@@ -111,34 +122,93 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
     } while (0)
 
 int sum_to_host(isam_plan_t p, const float* partials, int nblocks, int nslots, int mode_max, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, partials, nblocks, nslots, p->red.sums, mode_max);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, partials, nblocks, nslots, p->red.sums, mode_max);
     HIP_OK(hipGetLastError());
     HIP_OK(hipMemcpyAsync(p->host_sums, p->red.sums, nslots * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
     return ISAM_OK;
 }
 
+// Per-pass timing: an event pair around each pass while isam_timing is enabled.
+int tbegin(isam_plan_t p, int tag, hipStream_t s) {
+    if (!p->timing_on) return -1;
+    if (p->tev_used == p->tev_cap) {
+        const int cap = std::max(256, 2 * p->tev_cap);
+        hipEvent_t* ev = new (std::nothrow) hipEvent_t[2 * cap];
+        int* tg = new (std::nothrow) int[cap];
+        if (!ev || !tg) {
+            delete[] ev;
+            delete[] tg;
+            return -1;
+        }
+        for (int i = 0; i < 2 * p->tev_cap; ++i) ev[i] = p->tev[i];
+        for (int i = 0; i < p->tev_cap; ++i) tg[i] = p->ttag[i];
+        for (int i = 2 * p->tev_cap; i < 2 * cap; ++i)
+            if (hipEventCreate(&ev[i]) != hipSuccess) ev[i] = nullptr;
+        delete[] p->tev;
+        delete[] p->ttag;
+        p->tev = ev;
+        p->ttag = tg;
+        p->tev_cap = cap;
+    }
+    const int i = p->tev_used;
+    if (!p->tev[2 * i] || !p->tev[2 * i + 1]) return -1;
+    p->tev_used++;
+    p->ttag[i] = tag;
+    p->tstream = s;
+    (void)hipEventRecord(p->tev[2 * i], s);
+    return i;
+}
+
+void tend(isam_plan_t p, int i, hipStream_t s) {
+    if (i >= 0) (void)hipEventRecord(p->tev[2 * i + 1], s);
+}
+
+}  // namespace
+
+// Sum the recorded pairs into the per-pass totals (the stream must have completed them).
+void isam_timing_collect(isam_plan_t p) {
+    for (int i = 0; i < p->tev_used; ++i) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p->tev[2 * i], p->tev[2 * i + 1]) == hipSuccess) {
+            p->tms[p->ttag[i]] += ms;
+            p->tcnt[p->ttag[i]] += 1;
+        }
+    }
+    p->tev_used = 0;
+}
+
+namespace {
+
+#define TIMED(tag, expr)                               \
+    do {                                               \
+        const int t_ = tbegin(p, tag, s);              \
+        const hipError_t e_ = (expr);                  \
+        tend(p, t_, s);                                \
+        if (e_ != hipSuccess) return ISAM_EHIP;        \
+    } while (0)
+
 int forward_impl(isam_plan_t p, const float2* eta, float* s_out, hipStream_t s) {
-    HIP_OK(lat_c2c(p, eta, p->etahat, -1, s));
-    HIP_OK(nufft_fwd(p, p->etahat, p->zh, s));
-    HIP_OK(lat_c2r(p, p->zh, s_out, s));
+    TIMED(0, lat_c2c(p, eta, p->etahat, -1, s));
+    TIMED(1, nufft_fwd(p, p->etahat, p->zh, s));
+    TIMED(2, lat_c2r(p, p->zh, s_out, s));
     return ISAM_OK;
 }
 
 int adjoint_impl(isam_plan_t p, const float* r, float2* eta_out, hipStream_t s) {
-    HIP_OK(lat_r2c(p, r, p->rh, s));
-    HIP_OK(nufft_adj(p, p->rh, p->ghat, s));
-    HIP_OK(lat_c2c(p, p->ghat, eta_out, +1, s));
+    TIMED(3, lat_r2c(p, r, p->rh, s));
+    TIMED(4, nufft_adj(p, p->rh, p->ghat, s));
+    TIMED(5, lat_c2c(p, p->ghat, eta_out, +1, s));
     return ISAM_OK;
 }
 
 // out = A^H (A eta - y) (y may be null); ||A eta - y||^2 partials in red.partials slot 0.
 int normal_impl(isam_plan_t p, const float2* eta, const float* y, float2* out, hipStream_t s) {
-    HIP_OK(lat_c2c(p, eta, p->etahat, -1, s));
-    HIP_OK(nufft_fwd(p, p->etahat, p->zh, s));
-    HIP_OK(lat_resid(p, p->zh, y, p->rh, p->red.partials, s));
-    HIP_OK(nufft_adj(p, p->rh, p->ghat, s));
-    HIP_OK(lat_c2c(p, p->ghat, out, +1, s));
+    TIMED(0, lat_c2c(p, eta, p->etahat, -1, s));
+    TIMED(1, nufft_fwd(p, p->etahat, p->zh, s));
+    TIMED(6, lat_resid(p, p->zh, y, p->rh, p->red.partials, s));
+    TIMED(4, nufft_adj(p, p->rh, p->ghat, s));
+    TIMED(5, lat_c2c(p, p->ghat, out, +1, s));
     return ISAM_OK;
 }
 
@@ -181,21 +251,22 @@ extern "C" int isam_lipschitz(isam_plan_t p, int iters, uint64_t seed, const voi
     const int rb = lat_blocks(p, 1);
     // normalise the start vector into red.sums[1]
     hipLaunchKernelGGL(k_sumsq, dim3(gb), dim3(256), 0, s, x, n, p->red.partials);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, p->red.partials, gb, 1, p->red.sums + 1, 0);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, p->red.partials, gb, 1, p->red.sums + 1, 0);
     hipLaunchKernelGGL(k_scale_inv_sqrt, dim3(gb), dim3(256), 0, s, x, n, p->red.sums, 1);
     HIP_OK(hipGetLastError());
     for (int it = 0; it < iters; ++it) {
         // ||A x||^2 (the Rayleigh quotient, ||x|| = 1) lands in sums[0]; x <- A^H A x / ||.||
         int rc = normal_impl(p, x, nullptr, x, s);   // in-place lateral pass is safe (tile-local)
         if (rc) return rc;
-        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, p->red.partials, rb, 1, p->red.sums, 0);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, p->red.partials, rb, 1, p->red.sums, 0);
         hipLaunchKernelGGL(k_sumsq, dim3(gb), dim3(256), 0, s, x, n, p->red.partials);
-        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, p->red.partials, gb, 1, p->red.sums + 1, 0);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, p->red.partials, gb, 1, p->red.sums + 1, 0);
         hipLaunchKernelGGL(k_scale_inv_sqrt, dim3(gb), dim3(256), 0, s, x, n, p->red.sums, 1);
         HIP_OK(hipGetLastError());
     }
     HIP_OK(hipMemcpyAsync(p->host_sums, p->red.sums, sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
+    isam_timing_collect(p);
     const double ray = p->host_sums[0];
     if (!std::isfinite(ray)) return ISAM_ENONFINITE;
     *L_out = 1.01 * ray;
@@ -246,12 +317,12 @@ extern "C" int isam_fista(isam_plan_t p, const float* y, float lambda, const flo
     double t = 1.0, rel_res = -1.0;
     int k = 0, status = ISAM_OK;
     for (k = 1; k <= max_iter; ++k) {
-        HIP_OK(nufft_fwd(p, p->fista_hat, p->zh, s));
-        HIP_OK(lat_resid(p, p->zh, y, p->rh, part_r, s));
-        HIP_OK(nufft_adj(p, p->rh, p->ghat, s));
+        TIMED(1, nufft_fwd(p, p->fista_hat, p->zh, s));
+        TIMED(6, lat_resid(p, p->zh, y, p->rh, part_r, s));
+        TIMED(4, nufft_adj(p, p->rh, p->ghat, s));
         const double t_next = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
         fs.beta = (float)((t - 1.0) / t_next);
-        HIP_OK(lat_fista(p, p->fista_hat, p->ghat, z, w, fs, part_f, s));
+        TIMED(7, lat_fista(p, p->fista_hat, p->ghat, z, w, fs, part_f, s));
         if (fs.norms) {
             const int rc = sum_to_host(p, part_f, fb, 4, 0, s);
             if (rc) return rc;
@@ -284,6 +355,7 @@ extern "C" int isam_fista(isam_plan_t p, const float* y, float lambda, const flo
         HIP_OK(hipGetLastError());
     }
     HIP_OK(hipStreamSynchronize(s));
+    isam_timing_collect(p);
     if (info) {
         info->iters_run = iters_run;
         info->status = status;
@@ -293,4 +365,23 @@ extern "C" int isam_fista(isam_plan_t p, const float* y, float lambda, const flo
         info->L = L;
     }
     return status;
+}
+
+extern "C" int isam_timing(isam_plan_t p, int enable, double* ms_out, int64_t* count_out) {
+    if (!p) return ISAM_EINVAL;
+    if (p->tev_used > 0) {
+        if (hipStreamSynchronize(p->tstream) != hipSuccess) return ISAM_EHIP;
+        isam_timing_collect(p);
+    }
+    if (ms_out)
+        for (int i = 0; i < ISAM_NPASS; ++i) ms_out[i] = p->tms[i];
+    if (count_out)
+        for (int i = 0; i < ISAM_NPASS; ++i) count_out[i] = p->tcnt[i];
+    if (enable && !p->timing_on)
+        for (int i = 0; i < ISAM_NPASS; ++i) {
+            p->tms[i] = 0.0;
+            p->tcnt[i] = 0;
+        }
+    p->timing_on = enable ? 1 : 0;
+    return ISAM_OK;
 }

@@ -5,12 +5,15 @@
 //   e^{i phi(k_n)} e^{2 i k_n z_f}      dispersion phase (Eq. 7, 13) and focal reference
 //   s_m                                 Kaiser-Bessel scaling of the NUFFT
 //   u_j(tau)                            min-max interpolation weights as a piecewise cubic in tau
-//   twiddles                            exp(-2 pi i e / N) for the depth and lateral FFTs
+//   twiddles                            staged per FFT pass for the depth and lateral FFTs
+#include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
 #include "common.hpp"
+#include "fft.hpp"
 #include "plan.hpp"
 
 using namespace isam;
@@ -42,8 +45,6 @@ struct TableArgs {
     float* Bl;
     float2* En;
     float* sm;
-    float2* twK;
-    float2* twX;
 };
 
 // Kaiser-Bessel scaling s_m = Psi(0) / Psi(m / K), Psi(u) = sinh(a) / a, a = sqrt(beta^2 - (pi J u)^2).
@@ -60,9 +61,6 @@ __global__ void k_tables(TableArgs a) {
         const double q = 2.0 * kPi * l / (a.nx * a.dx);
         a.q2[i] = q * q;
         a.Bl[i] = (float)exp(-q * q * a.waist * a.waist / 8.0);
-        double sn, cs;
-        sincospi(-2.0 * i / a.nx, &sn, &cs);
-        a.twX[i] = make_float2((float)cs, (float)sn);
     }
     if (i < a.nk) {
         const double d = (i - a.nk / 2) * a.dk;                   // k_n - k0
@@ -75,10 +73,15 @@ __global__ void k_tables(TableArgs a) {
         a.En[i] = make_float2((float)(cs * norm), (float)(sn * norm));
         a.sm[i] = (float)kb_scale(i - a.nk / 2, a.K, a.beta);
     }
-    if (i < a.K) {
+}
+
+// Staged FFT twiddles (see fft.hpp) from a host-built (exponent, period) list, FP64.
+__global__ void k_twiddles(const int2* __restrict__ ep, int n, float2* __restrict__ tw) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
         double sn, cs;
-        sincospi(-2.0 * i / a.K, &sn, &cs);
-        a.twK[i] = make_float2((float)cs, (float)sn);
+        sincospi(-2.0 * ep[i].x / ep[i].y, &sn, &cs);
+        tw[i] = make_float2((float)cs, (float)sn);
     }
 }
 
@@ -292,6 +295,32 @@ void derive(isam_plan_s* p, const isam_geometry* g) {
         if ((x) != hipSuccess) return ISAM_EHIP;    \
     } while (0)
 
+int build_twiddles(isam_plan_s* p, hipStream_t s) {
+    const int PK = ilog2(p->K), PX = ilog2(p->nx);
+    const int nK = fft_stage_size(PK, 4), nK8 = fft_stage_size(PK, 3), nX = fft_stage_size(PX, 4);
+    const int ntot = nK + nK8 + nX;
+    int2* h = nullptr;
+    if (hipHostMalloc((void**)&h, (size_t)ntot * sizeof(int2)) != hipSuccess) return ISAM_ENOMEM;
+    for (int e = 0; e < nK; ++e) fft_stage_entry(PK, 4, e, h[e].x, h[e].y);
+    for (int e = 0; e < nK8; ++e) fft_stage_entry(PK, 3, e, h[nK + e].x, h[nK + e].y);
+    for (int e = 0; e < nX; ++e) fft_stage_entry(PX, 4, e, h[nK + nK8 + e].x, h[nK + nK8 + e].y);
+    int2* d = nullptr;
+    int rc = ISAM_OK;
+    if (hipMalloc((void**)&d, (size_t)ntot * sizeof(int2)) != hipSuccess) rc = ISAM_ENOMEM;
+    if (rc == ISAM_OK && hipMemcpyAsync(d, h, (size_t)ntot * sizeof(int2), hipMemcpyHostToDevice, s) != hipSuccess)
+        rc = ISAM_EHIP;
+    if (rc == ISAM_OK) {
+        hipLaunchKernelGGL(k_twiddles, dim3((nK + 255) / 256), dim3(256), 0, s, d, nK, p->twK);
+        hipLaunchKernelGGL(k_twiddles, dim3((nK8 + 255) / 256), dim3(256), 0, s, d + nK, nK8, p->twK8);
+        hipLaunchKernelGGL(k_twiddles, dim3((nX + 255) / 256), dim3(256), 0, s, d + nK + nK8, nX, p->twX);
+        if (hipGetLastError() != hipSuccess) rc = ISAM_EHIP;
+    }
+    if (hipStreamSynchronize(s) != hipSuccess && rc == ISAM_OK) rc = ISAM_EHIP;
+    if (d) (void)hipFree(d);
+    (void)hipHostFree(h);
+    return rc;
+}
+
 int build_calibrated_tables(isam_plan_s* p, hipStream_t s) {
     TableArgs a;
     a.nx = p->nx;
@@ -309,9 +338,7 @@ int build_calibrated_tables(isam_plan_s* p, hipStream_t s) {
     a.Bl = p->Bl;
     a.En = p->En;
     a.sm = p->sm;
-    a.twK = p->twK;
-    a.twX = p->twX;
-    const int n = std::max(p->K, std::max(p->nx, p->nk));
+    const int n = std::max(p->nx, p->nk);
     hipLaunchKernelGGL(k_tables, dim3((n + 255) / 256), dim3(256), 0, s, a);
     HIP_TRY(hipGetLastError());
 
@@ -345,12 +372,16 @@ int dalloc(T** ptr, size_t n) {
 }
 
 void release(isam_plan_s* p) {
-    void* ptrs[] = {p->q2, p->Bl, p->En, p->sm, p->wtab, p->twK, p->twX, p->wscratch,
+    void* ptrs[] = {p->q2, p->Bl, p->En, p->sm, p->wtab, p->twK, p->twK8, p->twX, p->wscratch,
                     p->etahat, p->zh, p->rh, p->ghat, p->fista_hat, p->vec, p->sbuf,
                     p->red.partials, p->red.sums};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     if (p->host_sums) (void)hipHostFree(p->host_sums);
+    for (int i = 0; i < 2 * p->tev_cap; ++i)
+        if (p->tev[i]) (void)hipEventDestroy(p->tev[i]);
+    delete[] p->tev;
+    delete[] p->ttag;
     delete p;
 }
 
@@ -373,6 +404,7 @@ isam::NufftArgs isam_plan_s::nufft_args() const {
     a.sm = sm;
     a.wtab = wtab;
     a.tw = twK;
+    a.tw8 = twK8;
     return a;
 }
 
@@ -394,6 +426,7 @@ extern "C" int isam_plan(const isam_geometry* g, void* stream, isam_plan_t* out)
     if (!p) return ISAM_ENOMEM;
     derive(p, g);
     p->device = dev;
+    if (const char* env = std::getenv("ISAM_LAT_C")) p->lat_c = std::atoi(env);
     const size_t full = (size_t)p->nx * p->nk, half = (size_t)p->nh * p->nk;
     p->red.maxBlocks = std::max(std::max(p->nx, p->nk), 2048) + 64;
     const int nsums = kPieces * 4 * kJ + (2 * kJ - 1);
@@ -403,8 +436,9 @@ extern "C" int isam_plan(const isam_geometry* g, void* stream, isam_plan_t* out)
     rc = rc ? rc : dalloc(&p->En, p->nk);
     rc = rc ? rc : dalloc(&p->sm, p->nk);
     rc = rc ? rc : dalloc(&p->wtab, kWtabEntries);
-    rc = rc ? rc : dalloc(&p->twK, p->K);
-    rc = rc ? rc : dalloc(&p->twX, std::max(p->nx, 1));
+    rc = rc ? rc : dalloc(&p->twK, fft_stage_size(ilog2(p->K), 4));
+    rc = rc ? rc : dalloc(&p->twK8, fft_stage_size(ilog2(p->K), 3));
+    rc = rc ? rc : dalloc(&p->twX, fft_stage_size(ilog2(p->nx)));
     rc = rc ? rc : dalloc(&p->wscratch, 2 * nsums);
     rc = rc ? rc : dalloc(&p->etahat, full);
     rc = rc ? rc : dalloc(&p->zh, half);
@@ -418,6 +452,7 @@ extern "C" int isam_plan(const isam_geometry* g, void* stream, isam_plan_t* out)
     if (rc == ISAM_OK && hipHostMalloc((void**)&p->host_sums, kRedSlots * sizeof(double)) != hipSuccess)
         rc = ISAM_ENOMEM;
     hipStream_t s = (hipStream_t)stream;
+    if (rc == ISAM_OK) rc = build_twiddles(p, s);
     if (rc == ISAM_OK) rc = build_calibrated_tables(p, s);
     if (rc == ISAM_OK && hipStreamSynchronize(s) != hipSuccess) rc = ISAM_EHIP;
     if (rc != ISAM_OK) {

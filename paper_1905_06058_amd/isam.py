@@ -26,8 +26,11 @@ ERRORS = {
 EXPORTS = (
     "isam_plan", "isam_set_calibration", "isam_forward", "isam_adjoint", "isam_normal",
     "isam_lipschitz", "isam_lambda_max", "isam_fista", "isam_destroy", "isam_strerror",
-    "isam_plan_dims",
+    "isam_plan_dims", "isam_timing",
 )
+
+PASS_NAMES = ("lateral_fft_fwd", "nufft_fwd", "lateral_c2r", "lateral_r2c", "nufft_adj",
+              "lateral_fft_inv", "residual_pass", "fista_update")
 
 
 class IsamError(RuntimeError):
@@ -90,6 +93,7 @@ def load_library() -> ctypes.CDLL:
         lib.isam_strerror.argtypes = [ctypes.c_int]
         lib.isam_strerror.restype = ctypes.c_char_p
         lib.isam_plan_dims.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        lib.isam_timing.argtypes = [vp, ctypes.c_int, ctypes.POINTER(dbl), ctypes.POINTER(ctypes.c_int64)]
         for name in EXPORTS:
             if name not in ("isam_destroy", "isam_strerror"):
                 getattr(lib, name).restype = ctypes.c_int
@@ -166,6 +170,14 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+    def timing(self, enable: bool) -> dict:
+        """Per-pass event timing: returns {pass: (total_ms, launches)} accumulated so far and
+        then enables (clearing) or disables recording."""
+        ms = (ctypes.c_double * 8)()
+        cnt = (ctypes.c_int64 * 8)()
+        _check(self._lib.isam_timing(self._h, int(bool(enable)), ms, cnt), "isam_timing")
+        return {name: (ms[i], cnt[i]) for i, name in enumerate(PASS_NAMES)}
 
     def set_calibration(self, a2: float, a3: float, z_focus: float, stream=None) -> None:
         _check(self._lib.isam_set_calibration(self._h, a2, a3, z_focus, _stream(stream)),
