@@ -58,12 +58,11 @@ def pass_bytes(nx: int, nk: int, weighted: bool) -> dict:
     c, f = 8, 4
     return {
         "lateral_fft_fwd": 2 * c * full,
-        "nufft_fwd": c * full + c * half,
+        "nufft_fwd": c * full + 2 * c * half,      # in FISTA it also reads F(y)
         "lateral_c2r": c * half + f * full,
         "lateral_r2c": f * full + c * half,
         "nufft_adj": c * half + c * full,
         "lateral_fft_inv": 2 * c * full,
-        "residual_pass": c * half + f * full + c * half,
         "fista_update": 5 * c * full + (f * full if weighted else 0),
     }
 

@@ -144,12 +144,12 @@ int isam_fista(isam_plan_t p, const float* y, float lambda, const float* w, int 
  * times are summed when a call completes (calls that synchronise) or here.
  * ms_out[ISAM_NPASS] and count_out[ISAM_NPASS] (either may be NULL) receive
  * the summed milliseconds and launch counts per pass:
- *   0 lateral FFT (forward)          1 Stolt NUFFT forward
- *   2 lateral C2R                    3 lateral R2C
- *   4 Stolt NUFFT adjoint            5 lateral FFT (inverse)
- *   6 residual pass (C2R, -y, R2C)   7 FISTA update pass
+ *   0 lateral FFT (forward)          1 Stolt NUFFT forward (in FISTA: with the data
+ *   2 lateral C2R                      subtracted in lateral frequency)
+ *   3 lateral R2C                    4 Stolt NUFFT adjoint
+ *   5 lateral FFT (inverse)          6 FISTA update pass
  * Synchronises the plan's last stream before reading. */
-#define ISAM_NPASS 8
+#define ISAM_NPASS 7
 int isam_timing(isam_plan_t p, int enable, double* ms_out, int64_t* count_out);
 
 /* Release a plan (NULL is allowed). */

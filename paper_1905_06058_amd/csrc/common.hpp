@@ -47,7 +47,7 @@ ISAM_DEV float wave_max(float v) {
     return v;
 }
 
-// Block-wide sum of NV values per thread; thread 0 writes them to out[0..NV).
+// Block-wide sum of NV values per thread; threads 0..NV-1 write them to out[0..NV).
 // `scratch` must hold NV * (T / 64) floats.  Ends with a barrier.
 template <int T, int NV>
 ISAM_DEV void block_sum_store(float (&v)[NV], float* scratch, float* out) {
@@ -66,6 +66,13 @@ ISAM_DEV void block_sum_store(float (&v)[NV], float* scratch, float* out) {
     }
     __syncthreads();
 }
+
+// Internal arrays [rows][cols] exchanged between the lateral and the per-column passes use a
+// column-blocked layout: blocks of 8 consecutive columns, each block stored row by row, so
+// that a lateral tile of 8 columns is one contiguous run and a column is read in 64-byte
+// (complex) segments.  Element (r, c) sits at blk(r, c, rows).
+constexpr int kBlk = 8;
+ISAM_DEV size_t blk(int r, int c, int rows) { return ((size_t)(c >> 3) * rows + r) * kBlk + (c & 7); }
 
 // Maps launch order to tile order so that tiles sharing cache lines land on the
 // same XCD: workgroups are dispatched round-robin over the 8 XCDs, so block b

@@ -13,7 +13,8 @@
 //
 // A workgroup takes the lateral pair (l, nx - l) (workgroup 0: the self-paired l = 0 and
 // l = nx/2) and writes the Hermitian half Z[l] = (X[l] + conj X[nx - l]) / 2, which the
-// C2R lateral pass turns into Re(F^{-1} X) (Eq. 5).
+// C2R lateral pass turns into Re(F^{-1} X) (Eq. 5), or, in the solver, the residual
+// spectrum Z - F(y).
 //
 // Adjoint: the exact transpose, one column per workgroup.  The transposed interpolation
 // is formed without atomics (see k_nufft_adj): t_n increases by at least 2 per sample,
@@ -105,7 +106,7 @@ ISAM_DEV float2 modulation(const NufftArgs& a, float Bl, int n, double t) {
 }
 
 template <int K>
-ISAM_DEV void forward_column(const NufftArgs& a, const float2* __restrict__ src, int col, float2* buf,
+ISAM_DEV void forward_column(const NufftArgs& a, const float2* __restrict__ etahat, int col, float2* buf,
                              const float2* wt, float2 (&xt)[NuCfg<K>::NPT], int tid) {
     using Cf = NuCfg<K>;
     using F = typename Cf::Fwd;
@@ -118,7 +119,7 @@ ISAM_DEV void forward_column(const NufftArgs& a, const float2* __restrict__ src,
             for (int j = 0; j < Cf::RO; ++j) {
                 const int x = b + j * Cf::SPAN;
                 const int u = (x + a.mi + a.nk / 2) & (K - 1);      // depth index placed at x
-                v[i * Cf::RO + j] = u < a.nk ? cscale(src[u], a.sm[u]) : c2(0.f, 0.f);
+                v[i * Cf::RO + j] = u < a.nk ? cscale(etahat[blk(col, u, a.nx)], a.sm[u]) : c2(0.f, 0.f);
             }
         }
     }
@@ -161,9 +162,16 @@ ISAM_DEV void forward_column(const NufftArgs& a, const float2* __restrict__ src,
 // Block = two halves of T threads; half h transforms one column of the lateral pair
 // (l, nx - l) (block 0: the self-paired l = 0 and l = nx/2), then half 0 writes the
 // Hermitian combination.
+// With yhat (the lateral spectrum of measured spectra, blocked half), the kernel writes the
+// residual spectrum R = Z - yhat instead of Z: for a unitary lateral DFT F,
+// F(Re F^{-1} X) is the Hermitian part Z of X, so the lateral transform of the residual
+// Re(F^{-1} X) - y needs no transform at all.  Partials of ||r||^2 = sum_l w_l |R_l|^2
+// (Parseval over the half spectrum, w = 1 at l = 0 and nx/2, else 2) go to partials.
 template <int K>
 __global__ __launch_bounds__(2 * NuCfg<K>::T) void k_nufft_fwd(const float2* __restrict__ etahat,
-                                                               float2* __restrict__ zh, NufftArgs a) {
+                                                               const float2* __restrict__ yhat,
+                                                               float2* __restrict__ zh, NufftArgs a,
+                                                               float* __restrict__ partials) {
     using Cf = NuCfg<K>;
     extern __shared__ float2 smem[];
     const int half = threadIdx.x / Cf::T, tid = threadIdx.x % Cf::T;
@@ -175,7 +183,7 @@ __global__ __launch_bounds__(2 * NuCfg<K>::T) void k_nufft_fwd(const float2* __r
     const int colB = b == 0 ? (a.nx >= 2 ? a.nx / 2 : -1) : a.nx - b;
     const int col = half == 0 ? colA : (colB >= 0 ? colB : colA);
     float2 xt[Cf::NPT];
-    forward_column<K>(a, etahat + (size_t)col * a.nk, col, buf, wt, xt, tid);
+    forward_column<K>(a, etahat, col, buf, wt, xt, tid);
     __syncthreads();
     if (half == 1) {
 #pragma unroll
@@ -185,20 +193,37 @@ __global__ __launch_bounds__(2 * NuCfg<K>::T) void k_nufft_fwd(const float2* __r
         }
     }
     __syncthreads();
+    float acc[1] = {0.f};
     if (half == 0) {
         const float2* other = smem + Cf::BUF;
+        const int nh = a.nx / 2 + 1;
 #pragma unroll
         for (int r = 0; r < Cf::NPT; ++r) {
             const int n = tid + r * Cf::T;
             if (n >= a.nk) continue;
             const float2 xb = other[n];
             if (b == 0) {
-                zh[n] = c2(xt[r].x, 0.f);
-                if (colB >= 0) zh[(size_t)colB * a.nk + n] = c2(xb.x, 0.f);
+                float2 z0 = c2(xt[r].x, 0.f);
+                if (yhat) z0 = csub(z0, yhat[blk(0, n, nh)]);
+                zh[blk(0, n, nh)] = z0;
+                acc[0] += cabs2(z0);
+                if (colB >= 0) {
+                    float2 z1 = c2(xb.x, 0.f);
+                    if (yhat) z1 = csub(z1, yhat[blk(colB, n, nh)]);
+                    zh[blk(colB, n, nh)] = z1;
+                    acc[0] += cabs2(z1);
+                }
             } else {
-                zh[(size_t)b * a.nk + n] = cscale(cadd(xt[r], cconj(xb)), 0.5f);
+                float2 z = cscale(cadd(xt[r], cconj(xb)), 0.5f);
+                if (yhat) z = csub(z, yhat[blk(b, n, nh)]);
+                zh[blk(b, n, nh)] = z;
+                acc[0] += 2.f * cabs2(z);
             }
         }
+    }
+    if (partials) {
+        __syncthreads();
+        block_sum_store<2 * Cf::T, 1>(acc, reinterpret_cast<float*>(smem), partials + blockIdx.x * kRedSlots);
     }
 }
 
@@ -240,7 +265,7 @@ __global__ __launch_bounds__(NuAdjCfg<K>::T) void k_nufft_adj(const float2* __re
         const bool prop = mine && stolt_point(a, q2, n, t, fl, tau);
         float2 vn = c2(0.f, 0.f);
         if (prop) {
-            float2 x = rh[(size_t)row * a.nk + n];
+            float2 x = rh[blk(row, n, a.nx / 2 + 1)];
             if (conj_in) x = cconj(x);
             vn = cmulc(x, modulation(a, Bl, n, t));
         }
@@ -291,7 +316,6 @@ __global__ __launch_bounds__(NuAdjCfg<K>::T) void k_nufft_adj(const float2* __re
         }
     }
     F::run(v, Y, a.tw8, tid);         // opens with a barrier: the reads of Y above are done
-    float2* dst = ghat + (size_t)col * a.nk;
 #pragma unroll
     for (int i = 0; i < F::BPTO; ++i) {
         int cc, b;
@@ -300,7 +324,7 @@ __global__ __launch_bounds__(NuAdjCfg<K>::T) void k_nufft_adj(const float2* __re
             for (int j = 0; j < Cf::RO; ++j) {
                 const int x = b + j * Cf::SPAN;
                 const int u = (x + a.mi + a.nk / 2) & (K - 1);
-                if (u < a.nk) dst[u] = cscale(v[i * Cf::RO + j], a.sm[u]);
+                if (u < a.nk) ghat[blk(col, u, a.nx)] = cscale(v[i * Cf::RO + j], a.sm[u]);
             }
         }
     }
@@ -313,11 +337,12 @@ void set_lds(Kern kern, size_t bytes) {
 }
 
 template <int K>
-hipError_t launch_fwd(const isam_plan_s* p, const float2* etahat, float2* zh, hipStream_t s) {
+hipError_t launch_fwd(const isam_plan_s* p, const float2* etahat, const float2* yhat, float2* zh, float* partials,
+                      hipStream_t s) {
     using Cf = NuCfg<K>;
     set_lds(k_nufft_fwd<K>, Cf::LDS_FWD);
     hipLaunchKernelGGL(k_nufft_fwd<K>, dim3(std::max(1, p->nx / 2)), dim3(2 * Cf::T), Cf::LDS_FWD, s, etahat,
-                       zh, p->nufft_args());
+                       yhat, zh, p->nufft_args(), partials);
     return hipGetLastError();
 }
 
@@ -359,8 +384,9 @@ hipError_t launch_adj(const isam_plan_s* p, const float2* rh, float2* ghat, hipS
         default: return 0;                          \
     }
 
-hipError_t nufft_fwd(const isam_plan_s* p, const float2* etahat, float2* zh, hipStream_t s) {
-    ISAM_K_SWITCH(p->K, return launch_fwd<K>(p, etahat, zh, s));
+hipError_t nufft_fwd(const isam_plan_s* p, const float2* etahat, const float2* yhat, float2* zh, float* partials,
+                     hipStream_t s) {
+    ISAM_K_SWITCH(p->K, return launch_fwd<K>(p, etahat, yhat, zh, partials, s));
 }
 
 hipError_t nufft_adj(const isam_plan_s* p, const float2* rh, float2* ghat, hipStream_t s) {
@@ -372,6 +398,8 @@ hipError_t nufft_adj(const isam_plan_s* p, const float2* rh, float2* ghat, hipSt
 // any propagating component), so no two samples share a slot of a cell; (2) the cells of a
 // chunk of samples, [g0_first + 1, g0_last + J], fit the chunk's slot array.  A margin of
 // a few cells covers FP64 rounding differences between host and device at floor boundaries.
+int nufft_fwd_blocks(const isam_plan_s* p) { return std::max(1, p->nx / 2); }
+
 int nufft_span_ok(const isam_plan_s* p) {
     int cs = 64;
     int slotc = 0;

@@ -44,7 +44,8 @@ struct isam_plan_s {
     double kc, band, dk, dz, cT, beta, mf;
     int mi;
     double mr;
-    int lat_c = 0;                // lateral tile width (complex lanes); 0 = default for nx
+    int lat_c = 0;                // lateral tile width of complex passes (lanes); 0 = default
+    int lat_cr = 0;               // lateral tile width of real passes (lanes); 0 = default
 
     // tables (device)
     double* q2 = nullptr;
@@ -54,17 +55,21 @@ struct isam_plan_s {
     float2* wtab = nullptr;
     float2* twK = nullptr;
     float2* twK8 = nullptr;
-    float2* twX = nullptr;
+    float2* twX[5] = {};          // staged lateral twiddles for radix caps 2^2, 2^3, 2^4 (index = log2 cap)
     double* wscratch = nullptr;   // FP64 scratch of the weight-table build
 
     // workspace (device)
+    // lateral-frequency arrays, column-blocked (see blk in common.hpp)
     float2* etahat = nullptr;     // [nx][nk] lateral spectrum of the operator input
     float2* zh = nullptr;         // [nh][nk] Hermitian half of the forward spectrum
     float2* rh = nullptr;         // [nh][nk] half spectrum of a real residual
     float2* ghat = nullptr;       // [nx][nk] lateral spectrum of the adjoint output
     float2* fista_hat = nullptr;  // [nx][nk] FISTA momentum point in lateral frequency
+    float2* yhat = nullptr;       // [nh][nk] lateral spectrum of the measured spectra (FISTA)
     float2* vec = nullptr;        // [nx][nk] power-iteration vector
-    float* sbuf = nullptr;        // [nx][nk] real spectra scratch
+    float* sbuf = nullptr;        // [nx][nk] real spectra scratch (FISTA: blocked data y)
+    float* wbuf = nullptr;        // [nx][nk] blocked l1 weights of FISTA
+    float2* zblk = nullptr;       // [nx][nk] blocked FISTA iterate z
     isam::Reduce red;
     double* host_sums = nullptr;  // pinned host copy of red.sums
 
@@ -87,9 +92,6 @@ namespace isam {
 hipError_t lat_c2c(const isam_plan_s* p, const float2* in, float2* out, int sign, hipStream_t s);
 hipError_t lat_c2r(const isam_plan_s* p, const float2* zh, float* s_out, hipStream_t st);
 hipError_t lat_r2c(const isam_plan_s* p, const float* r, float2* rh, hipStream_t st);
-// residual pass: Zh -> s = C2R(Zh) -> r = s - y (y may be null) -> Rh = R2C(r); partial ||r||^2
-hipError_t lat_resid(const isam_plan_s* p, const float2* zh, const float* y, float2* rh,
-                     float* partials, hipStream_t st);
 // FISTA update pass; see solver.hip
 struct FistaStep {
     float step, lam, beta;
@@ -98,8 +100,13 @@ struct FistaStep {
 hipError_t lat_fista(const isam_plan_s* p, float2* eta_hat, const float2* ghat, float2* z,
                      const float* w, FistaStep fs, float* partials, hipStream_t st);
 int lat_blocks(const isam_plan_s* p, int kind);   // number of workgroups of a lateral pass
+int lat_l(const isam_plan_s* p);                  // radix cap (log2) of the lateral FFT
 
-hipError_t nufft_fwd(const isam_plan_s* p, const float2* etahat, float2* zh, hipStream_t s);
+// Forward Stolt NUFFT: zh = Z (yhat null) or the residual spectrum Z - yhat; ||.||^2 partials
+// (Parseval weights) per workgroup into partials slot 0 if partials is non-null.
+hipError_t nufft_fwd(const isam_plan_s* p, const float2* etahat, const float2* yhat, float2* zh, float* partials,
+                     hipStream_t s);
+int nufft_fwd_blocks(const isam_plan_s* p);
 hipError_t nufft_adj(const isam_plan_s* p, const float2* rh, float2* ghat, hipStream_t s);
 int nufft_span_ok(const isam_plan_s* p);          // host check of the Stolt span bound
 

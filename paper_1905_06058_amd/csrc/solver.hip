@@ -2,11 +2,11 @@
 //
 // isam_forward   s = Re(K^ eta)             lateral FFT -> NUFFT pairs -> C2R
 // isam_adjoint   eta = K^^H r               R2C -> transposed NUFFT pairs -> lateral IFFT
-// isam_normal    A^H A eta                  the C2R and R2C passes fused
-// isam_fista     per iteration: NUFFT (momentum point) -> residual pass (C2R, -y, R2C)
-//                -> transposed NUFFT -> update pass (IFFT, step, soft threshold, momentum,
-//                FFT of the next momentum point).  The momentum point is kept in lateral
-//                frequency, so an iteration is four passes.
+// isam_normal    A^H A eta                  lateral FFT -> NUFFT -> transposed NUFFT -> IFFT
+// isam_fista     per iteration: NUFFT of the momentum point with the data subtracted in
+//                lateral frequency -> transposed NUFFT -> update pass (IFFT, step, soft
+//                threshold, momentum, FFT of the next momentum point).  The momentum point
+//                is kept in lateral frequency, so an iteration is three passes.
 #include <algorithm>
 #include <cmath>
 #include <new>
@@ -82,6 +82,18 @@ __global__ void k_scale_inv_sqrt(float2* __restrict__ x, size_t n, const double*
 __global__ void k_axpy(float2* __restrict__ x, const float2* __restrict__ y, float a, size_t n) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         x[i] = csub(x[i], cscale(y[i], a));
+}
+
+// Row-major real [rows][cols] -> column-blocked, and column-blocked complex -> row-major.
+__global__ void k_to_blk_f(const float* __restrict__ src, float* __restrict__ dst, int rows, int cols) {
+    const size_t n = (size_t)rows * cols;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        dst[blk((int)(i / cols), (int)(i % cols), rows)] = src[i];
+}
+__global__ void k_from_blk_c(const float2* __restrict__ src, float2* __restrict__ dst, int rows, int cols) {
+    const size_t n = (size_t)rows * cols;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[blk((int)(i / cols), (int)(i % cols), rows)];
 }
 
 __global__ void k_zero(float2* __restrict__ x, size_t n) {
@@ -190,7 +202,7 @@ namespace {
 
 int forward_impl(isam_plan_t p, const float2* eta, float* s_out, hipStream_t s) {
     TIMED(0, lat_c2c(p, eta, p->etahat, -1, s));
-    TIMED(1, nufft_fwd(p, p->etahat, p->zh, s));
+    TIMED(1, nufft_fwd(p, p->etahat, nullptr, p->zh, nullptr, s));
     TIMED(2, lat_c2r(p, p->zh, s_out, s));
     return ISAM_OK;
 }
@@ -202,11 +214,13 @@ int adjoint_impl(isam_plan_t p, const float* r, float2* eta_out, hipStream_t s) 
     return ISAM_OK;
 }
 
-// out = A^H (A eta - y) (y may be null); ||A eta - y||^2 partials in red.partials slot 0.
-int normal_impl(isam_plan_t p, const float2* eta, const float* y, float2* out, hipStream_t s) {
+// out = A^H (A eta - y) (eta, out row-major; yhat = F(y) as a blocked half spectrum, or null).
+// The lateral transform of the residual is Z - yhat (see k_nufft_fwd), so the forward and
+// adjoint NUFFT passes meet in the lateral-frequency domain.  ||A eta - y||^2 partials go to
+// red.partials slot 0 (nufft_fwd_blocks workgroups).
+int normal_impl(isam_plan_t p, const float2* eta, const float2* yhat, float2* out, hipStream_t s) {
     TIMED(0, lat_c2c(p, eta, p->etahat, -1, s));
-    TIMED(1, nufft_fwd(p, p->etahat, p->zh, s));
-    TIMED(6, lat_resid(p, p->zh, y, p->rh, p->red.partials, s));
+    TIMED(1, nufft_fwd(p, p->etahat, yhat, p->rh, p->red.partials, s));
     TIMED(4, nufft_adj(p, p->rh, p->ghat, s));
     TIMED(5, lat_c2c(p, p->ghat, out, +1, s));
     return ISAM_OK;
@@ -248,7 +262,7 @@ extern "C" int isam_lipschitz(isam_plan_t p, int iters, uint64_t seed, const voi
         HIP_OK(hipGetLastError());
     }
     const int gb = grid_for(n);
-    const int rb = lat_blocks(p, 1);
+    const int rb = nufft_fwd_blocks(p);
     // normalise the start vector into red.sums[1]
     hipLaunchKernelGGL(k_sumsq, dim3(gb), dim3(256), 0, s, x, n, p->red.partials);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, p->red.partials, gb, 1, p->red.sums + 1, 0);
@@ -301,13 +315,18 @@ extern "C" int isam_fista(isam_plan_t p, const float* y, float lambda, const flo
         const int rc = isam_lipschitz(p, 50, 0, nullptr, &L, stream);
         if (rc) return rc;
     }
-    float2* z = (float2*)eta_out;
+    // FISTA state and weights in the column-blocked layout of the lateral passes; the data
+    // enter as their lateral spectrum yhat = F(y) (Hermitian half, blocked)
+    float2* z = p->zblk;
+    float* wb = w ? p->wbuf : nullptr;
     const int gb = grid_for(n);
     hipLaunchKernelGGL(k_zero, dim3(gb), dim3(256), 0, s, z, n);
     hipLaunchKernelGGL(k_zero, dim3(gb), dim3(256), 0, s, p->fista_hat, n);
+    if (w) hipLaunchKernelGGL(k_to_blk_f, dim3(gb), dim3(256), 0, s, w, wb, p->nx, p->nk);
     HIP_OK(hipGetLastError());
-    const int rb = lat_blocks(p, 1), fb = lat_blocks(p, 0);
-    float* part_r = p->red.partials;                       // residual pass, slot 0
+    TIMED(3, lat_r2c(p, y, p->yhat, s));
+    const int rb = nufft_fwd_blocks(p), fb = lat_blocks(p, 0);
+    float* part_r = p->red.partials;                            // forward NUFFT, slot 0
     float* part_f = p->red.partials + (size_t)rb * kRedSlots;   // update pass, slots 0..3
     if (rb + fb > p->red.maxBlocks) return ISAM_EUNSUPPORTED;
     FistaStep fs;
@@ -317,12 +336,11 @@ extern "C" int isam_fista(isam_plan_t p, const float* y, float lambda, const flo
     double t = 1.0, rel_res = -1.0;
     int k = 0, status = ISAM_OK;
     for (k = 1; k <= max_iter; ++k) {
-        TIMED(1, nufft_fwd(p, p->fista_hat, p->zh, s));
-        TIMED(6, lat_resid(p, p->zh, y, p->rh, part_r, s));
+        TIMED(1, nufft_fwd(p, p->fista_hat, p->yhat, p->rh, part_r, s));
         TIMED(4, nufft_adj(p, p->rh, p->ghat, s));
         const double t_next = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
         fs.beta = (float)((t - 1.0) / t_next);
-        TIMED(7, lat_fista(p, p->fista_hat, p->ghat, z, w, fs, part_f, s));
+        TIMED(6, lat_fista(p, p->fista_hat, p->ghat, z, wb, fs, part_f, s));
         if (fs.norms) {
             const int rc = sum_to_host(p, part_f, fb, 4, 0, s);
             if (rc) return rc;
@@ -347,11 +365,14 @@ extern "C" int isam_fista(isam_plan_t p, const float* y, float lambda, const flo
         l1 = p->host_sums[3];
         if (!std::isfinite(resid2) || !std::isfinite(l1)) status = ISAM_ENONFINITE;
     }
+    float2* out = (float2*)eta_out;
+    hipLaunchKernelGGL(k_from_blk_c, dim3(gb), dim3(256), 0, s, z, out, p->nx, p->nk);
+    HIP_OK(hipGetLastError());
     if (add_residual && status == ISAM_OK) {
         // z += (1/L) A^H (y - A z)  ==  z -= (1/L) A^H (A z - y)
-        int rc = normal_impl(p, z, y, p->vec, s);
+        int rc = normal_impl(p, out, p->yhat, p->vec, s);
         if (rc) return rc;
-        hipLaunchKernelGGL(k_axpy, dim3(gb), dim3(256), 0, s, z, p->vec, (float)(1.0 / L), n);
+        hipLaunchKernelGGL(k_axpy, dim3(gb), dim3(256), 0, s, out, p->vec, (float)(1.0 / L), n);
         HIP_OK(hipGetLastError());
     }
     HIP_OK(hipStreamSynchronize(s));

@@ -296,24 +296,34 @@ void derive(isam_plan_s* p, const isam_geometry* g) {
     } while (0)
 
 int build_twiddles(isam_plan_s* p, hipStream_t s) {
+    // staged tables: depth FFT (radix caps 16 and 8), lateral FFT (caps 4, 8, 16)
     const int PK = ilog2(p->K), PX = ilog2(p->nx);
-    const int nK = fft_stage_size(PK, 4), nK8 = fft_stage_size(PK, 3), nX = fft_stage_size(PX, 4);
-    const int ntot = nK + nK8 + nX;
+    struct Item { int P, L; float2* dst; };
+    const Item items[] = {{PK, 4, p->twK}, {PK, 3, p->twK8}, {PX, 2, p->twX[2]}, {PX, 3, p->twX[3]},
+                          {PX, 4, p->twX[4]}};
+    int ntot = 0;
+    for (const Item& it : items) ntot += fft_stage_size(it.P, it.L);
     int2* h = nullptr;
     if (hipHostMalloc((void**)&h, (size_t)ntot * sizeof(int2)) != hipSuccess) return ISAM_ENOMEM;
-    for (int e = 0; e < nK; ++e) fft_stage_entry(PK, 4, e, h[e].x, h[e].y);
-    for (int e = 0; e < nK8; ++e) fft_stage_entry(PK, 3, e, h[nK + e].x, h[nK + e].y);
-    for (int e = 0; e < nX; ++e) fft_stage_entry(PX, 4, e, h[nK + nK8 + e].x, h[nK + nK8 + e].y);
+    int off = 0;
+    for (const Item& it : items) {
+        const int n = fft_stage_size(it.P, it.L);
+        for (int e = 0; e < n; ++e) fft_stage_entry(it.P, it.L, e, h[off + e].x, h[off + e].y);
+        off += n;
+    }
     int2* d = nullptr;
     int rc = ISAM_OK;
     if (hipMalloc((void**)&d, (size_t)ntot * sizeof(int2)) != hipSuccess) rc = ISAM_ENOMEM;
     if (rc == ISAM_OK && hipMemcpyAsync(d, h, (size_t)ntot * sizeof(int2), hipMemcpyHostToDevice, s) != hipSuccess)
         rc = ISAM_EHIP;
-    if (rc == ISAM_OK) {
-        hipLaunchKernelGGL(k_twiddles, dim3((nK + 255) / 256), dim3(256), 0, s, d, nK, p->twK);
-        hipLaunchKernelGGL(k_twiddles, dim3((nK8 + 255) / 256), dim3(256), 0, s, d + nK, nK8, p->twK8);
-        hipLaunchKernelGGL(k_twiddles, dim3((nX + 255) / 256), dim3(256), 0, s, d + nK + nK8, nX, p->twX);
-        if (hipGetLastError() != hipSuccess) rc = ISAM_EHIP;
+    off = 0;
+    for (const Item& it : items) {
+        const int n = fft_stage_size(it.P, it.L);
+        if (rc == ISAM_OK) {
+            hipLaunchKernelGGL(k_twiddles, dim3((n + 255) / 256), dim3(256), 0, s, d + off, n, it.dst);
+            if (hipGetLastError() != hipSuccess) rc = ISAM_EHIP;
+        }
+        off += n;
     }
     if (hipStreamSynchronize(s) != hipSuccess && rc == ISAM_OK) rc = ISAM_EHIP;
     if (d) (void)hipFree(d);
@@ -372,8 +382,8 @@ int dalloc(T** ptr, size_t n) {
 }
 
 void release(isam_plan_s* p) {
-    void* ptrs[] = {p->q2, p->Bl, p->En, p->sm, p->wtab, p->twK, p->twK8, p->twX, p->wscratch,
-                    p->etahat, p->zh, p->rh, p->ghat, p->fista_hat, p->vec, p->sbuf,
+    void* ptrs[] = {p->q2, p->Bl, p->En, p->sm, p->wtab, p->twK, p->twK8, p->twX[2], p->twX[3], p->twX[4], p->wscratch,
+                    p->etahat, p->zh, p->rh, p->ghat, p->fista_hat, p->yhat, p->vec, p->sbuf, p->wbuf, p->zblk,
                     p->red.partials, p->red.sums};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
@@ -427,8 +437,9 @@ extern "C" int isam_plan(const isam_geometry* g, void* stream, isam_plan_t* out)
     derive(p, g);
     p->device = dev;
     if (const char* env = std::getenv("ISAM_LAT_C")) p->lat_c = std::atoi(env);
+    if (const char* env = std::getenv("ISAM_LAT_CR")) p->lat_cr = std::atoi(env);
     const size_t full = (size_t)p->nx * p->nk, half = (size_t)p->nh * p->nk;
-    p->red.maxBlocks = std::max(std::max(p->nx, p->nk), 2048) + 64;
+    p->red.maxBlocks = std::max(std::max(p->nx, 2 * p->nk), 2048) + 64;   // lateral passes use up to 2 nk blocks
     const int nsums = kPieces * 4 * kJ + (2 * kJ - 1);
     rc = ISAM_OK;
     rc = rc ? rc : dalloc(&p->q2, p->nx);
@@ -438,15 +449,18 @@ extern "C" int isam_plan(const isam_geometry* g, void* stream, isam_plan_t* out)
     rc = rc ? rc : dalloc(&p->wtab, kWtabEntries);
     rc = rc ? rc : dalloc(&p->twK, fft_stage_size(ilog2(p->K), 4));
     rc = rc ? rc : dalloc(&p->twK8, fft_stage_size(ilog2(p->K), 3));
-    rc = rc ? rc : dalloc(&p->twX, fft_stage_size(ilog2(p->nx)));
+    for (int L = 2; L <= 4; ++L) rc = rc ? rc : dalloc(&p->twX[L], fft_stage_size(ilog2(p->nx), L));
     rc = rc ? rc : dalloc(&p->wscratch, 2 * nsums);
     rc = rc ? rc : dalloc(&p->etahat, full);
     rc = rc ? rc : dalloc(&p->zh, half);
     rc = rc ? rc : dalloc(&p->rh, half);
     rc = rc ? rc : dalloc(&p->ghat, full);
     rc = rc ? rc : dalloc(&p->fista_hat, full);
+    rc = rc ? rc : dalloc(&p->yhat, half);
     rc = rc ? rc : dalloc(&p->vec, full);
     rc = rc ? rc : dalloc(&p->sbuf, full);
+    rc = rc ? rc : dalloc(&p->wbuf, full);
+    rc = rc ? rc : dalloc(&p->zblk, full);
     rc = rc ? rc : dalloc(&p->red.partials, (size_t)p->red.maxBlocks * kRedSlots);
     rc = rc ? rc : dalloc(&p->red.sums, kRedSlots);
     if (rc == ISAM_OK && hipHostMalloc((void**)&p->host_sums, kRedSlots * sizeof(double)) != hipSuccess)

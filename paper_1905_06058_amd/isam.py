@@ -30,7 +30,7 @@ EXPORTS = (
 )
 
 PASS_NAMES = ("lateral_fft_fwd", "nufft_fwd", "lateral_c2r", "lateral_r2c", "nufft_adj",
-              "lateral_fft_inv", "residual_pass", "fista_update")
+              "lateral_fft_inv", "fista_update")
 
 
 class IsamError(RuntimeError):
@@ -174,8 +174,8 @@ class Plan:
     def timing(self, enable: bool) -> dict:
         """Per-pass event timing: returns {pass: (total_ms, launches)} accumulated so far and
         then enables (clearing) or disables recording."""
-        ms = (ctypes.c_double * 8)()
-        cnt = (ctypes.c_int64 * 8)()
+        ms = (ctypes.c_double * len(PASS_NAMES))()
+        cnt = (ctypes.c_int64 * len(PASS_NAMES))()
         _check(self._lib.isam_timing(self._h, int(bool(enable)), ms, cnt), "isam_timing")
         return {name: (ms[i], cnt[i]) for i, name in enumerate(PASS_NAMES)}
 
