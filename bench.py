@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--cpu-sample-nx", type=int, default=64,
                     help="A-scans of the oracle's timing sample (same depth length and optics)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle timing budget")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first run a plain 64 MiB device copy (calibrates memory-traffic counters)")
     return ap.parse_args()
 
 
@@ -124,6 +126,13 @@ def main() -> int:
         print("bench.py: no GPU visible", file=sys.stderr)
         return 1
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        src = torch.ones(16 << 20, dtype=torch.float32, device="cuda")    # 64 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = ph.workload(args.workload)
     o = w.optics
     nx, nk = o.nx, o.nk

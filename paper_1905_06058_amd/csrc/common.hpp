@@ -72,7 +72,8 @@ ISAM_DEV void block_sum_store(float (&v)[NV], float* scratch, float* out) {
 // that a lateral tile of 8 columns is one contiguous run and a column is read in 64-byte
 // (complex) segments.  Element (r, c) sits at blk(r, c, rows).
 constexpr int kBlk = 8;
-ISAM_DEV size_t blk(int r, int c, int rows) { return ((size_t)(c >> 3) * rows + r) * kBlk + (c & 7); }
+// 32-bit offsets: internal arrays hold fewer than 2^31 elements (nx * nk <= 2^23).
+ISAM_DEV unsigned blk(int r, int c, int rows) { return ((unsigned)(c >> 3) * rows + r) * kBlk + (c & 7); }
 
 // Maps launch order to tile order so that tiles sharing cache lines land on the
 // same XCD: workgroups are dispatched round-robin over the 8 XCDs, so block b

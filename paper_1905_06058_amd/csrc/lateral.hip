@@ -63,7 +63,7 @@ __global__ __launch_bounds__((LatCfg<N, C>::T)) void k_lat_c2c(const float2* in,
         if (F::outer(threadIdx.x, i, c, b)) {
 #pragma unroll
             for (int j = 0; j < Cf::RO; ++j)
-                v[i * Cf::RO + j] = in[IB ? blk(b + j * Cf::SPAN, m0 + c, N) : (size_t)(b + j * Cf::SPAN) * nk + m0 + c];
+                v[i * Cf::RO + j] = in[IB ? blk(b + j * Cf::SPAN, m0 + c, N) : (unsigned)(b + j * Cf::SPAN) * nk + m0 + c];
         }
     }
     F::run(v, lds, tw, threadIdx.x);
@@ -73,7 +73,7 @@ __global__ __launch_bounds__((LatCfg<N, C>::T)) void k_lat_c2c(const float2* in,
         if (F::outer(threadIdx.x, i, c, b)) {
 #pragma unroll
             for (int j = 0; j < Cf::RO; ++j)
-                out[OB ? blk(b + j * Cf::SPAN, m0 + c, N) : (size_t)(b + j * Cf::SPAN) * nk + m0 + c] =
+                out[OB ? blk(b + j * Cf::SPAN, m0 + c, N) : (unsigned)(b + j * Cf::SPAN) * nk + m0 + c] =
                     cscale(v[i * Cf::RO + j], scale);
         }
     }
@@ -140,7 +140,7 @@ __global__ __launch_bounds__((LatCfg<N, C>::T)) void k_lat_c2r(const float2* __r
         if (F::outer(threadIdx.x, i, c, b)) {
 #pragma unroll
             for (int j = 0; j < Cf::RO; ++j)
-                *reinterpret_cast<float2*>(s + (size_t)(b + j * Cf::SPAN) * nk + n0 + 2 * c) =
+                *reinterpret_cast<float2*>(s + (unsigned)(b + j * Cf::SPAN) * nk + n0 + 2 * c) =
                     cscale(v[i * Cf::RO + j], scale);
         }
     }
@@ -162,7 +162,7 @@ __global__ __launch_bounds__((LatCfg<N, C>::T)) void k_lat_r2c(const float* __re
 #pragma unroll
             for (int j = 0; j < Cf::RO; ++j)
                 v[i * Cf::RO + j] =
-                    *reinterpret_cast<const float2*>(r + (size_t)(b + j * Cf::SPAN) * nk + n0 + 2 * c);
+                    *reinterpret_cast<const float2*>(r + (unsigned)(b + j * Cf::SPAN) * nk + n0 + 2 * c);
         }
     }
     F::run(v, lds, tw, threadIdx.x);

@@ -93,8 +93,8 @@ ISAM_DEV float2 weight(const float2* wt, float tau, int jj) {
 }
 
 // The per-sample modulation B_l E_n f_n (f_n only with a fractional focal row).
-ISAM_DEV float2 modulation(const NufftArgs& a, float Bl, int n, double t) {
-    float2 e = cscale(a.En[n], Bl);
+ISAM_DEV float2 modulation(const NufftArgs& a, float2 En, float Bl, double t) {
+    float2 e = cscale(En, Bl);
     if (a.has_frac) {
         double ph = a.mr_over_K * t;
         ph -= rint(ph);
@@ -110,6 +110,9 @@ ISAM_DEV void forward_column(const NufftArgs& a, const float2* __restrict__ etah
                              const float2* wt, float2 (&xt)[NuCfg<K>::NPT], int tid) {
     using Cf = NuCfg<K>;
     using F = typename Cf::Fwd;
+    float2 en[Cf::NPT];                     // e^{i phi} e^{2 i k z_f} / sqrt(nz) of the thread's samples
+#pragma unroll
+    for (int r = 0; r < Cf::NPT; ++r) en[r] = a.En[min(tid + r * Cf::T, a.nk - 1)];
     float2 v[F::EPT];
 #pragma unroll
     for (int i = 0; i < F::BPTO; ++i) {
@@ -119,7 +122,9 @@ ISAM_DEV void forward_column(const NufftArgs& a, const float2* __restrict__ etah
             for (int j = 0; j < Cf::RO; ++j) {
                 const int x = b + j * Cf::SPAN;
                 const int u = (x + a.mi + a.nk / 2) & (K - 1);      // depth index placed at x
-                v[i * Cf::RO + j] = u < a.nk ? cscale(etahat[blk(col, u, a.nx)], a.sm[u]) : c2(0.f, 0.f);
+                const int uc = u < a.nk ? u : 0;
+                const float2 e = cscale(etahat[blk(col, uc, a.nx)], a.sm[uc]);
+                v[i * Cf::RO + j] = u < a.nk ? e : c2(0.f, 0.f);
             }
         }
     }
@@ -153,7 +158,7 @@ ISAM_DEV void forward_column(const NufftArgs& a, const float2* __restrict__ etah
             float2 acc = c2(0.f, 0.f);
 #pragma unroll
             for (int jj = 0; jj < kJ; ++jj) acc = cfma(weight(wt, tau, jj), y[jj], acc);
-            out = cmul(acc, modulation(a, Bl, n, t));
+            out = cmul(acc, modulation(a, en[r], Bl, t));
         }
         xt[r] = out;
     }
@@ -178,12 +183,20 @@ __global__ __launch_bounds__(2 * NuCfg<K>::T) void k_nufft_fwd(const float2* __r
     float2* buf = smem + half * Cf::BUF;
     float2* wt = smem + 2 * Cf::BUF;
     for (int i = threadIdx.x; i < kWtabEntries; i += 2 * Cf::T) wt[i] = a.wtab[i];
-    const int b = blockIdx.x;
+    const int b = xcd_tile(blockIdx.x, gridDim.x);     // neighbouring pairs on one XCD
     const int colA = b;
     const int colB = b == 0 ? (a.nx >= 2 ? a.nx / 2 : -1) : a.nx - b;
     const int col = half == 0 ? colA : (colB >= 0 ? colB : colA);
     float2 xt[Cf::NPT];
     forward_column<K>(a, etahat, col, buf, wt, xt, tid);
+    const int nh = a.nx / 2 + 1;
+    float2 yh[Cf::NPT], yh1[Cf::NPT];
+#pragma unroll
+    for (int r = 0; r < Cf::NPT; ++r) {
+        const int n = min(tid + r * Cf::T, a.nk - 1);
+        yh[r] = yhat && half == 0 ? yhat[blk(b, n, nh)] : c2(0.f, 0.f);
+        yh1[r] = yhat && half == 0 && b == 0 && colB >= 0 ? yhat[blk(colB, n, nh)] : c2(0.f, 0.f);
+    }
     __syncthreads();
     if (half == 1) {
 #pragma unroll
@@ -196,26 +209,22 @@ __global__ __launch_bounds__(2 * NuCfg<K>::T) void k_nufft_fwd(const float2* __r
     float acc[1] = {0.f};
     if (half == 0) {
         const float2* other = smem + Cf::BUF;
-        const int nh = a.nx / 2 + 1;
 #pragma unroll
         for (int r = 0; r < Cf::NPT; ++r) {
             const int n = tid + r * Cf::T;
             if (n >= a.nk) continue;
             const float2 xb = other[n];
             if (b == 0) {
-                float2 z0 = c2(xt[r].x, 0.f);
-                if (yhat) z0 = csub(z0, yhat[blk(0, n, nh)]);
+                const float2 z0 = csub(c2(xt[r].x, 0.f), yh[r]);
                 zh[blk(0, n, nh)] = z0;
                 acc[0] += cabs2(z0);
                 if (colB >= 0) {
-                    float2 z1 = c2(xb.x, 0.f);
-                    if (yhat) z1 = csub(z1, yhat[blk(colB, n, nh)]);
+                    const float2 z1 = csub(c2(xb.x, 0.f), yh1[r]);
                     zh[blk(colB, n, nh)] = z1;
                     acc[0] += cabs2(z1);
                 }
             } else {
-                float2 z = cscale(cadd(xt[r], cconj(xb)), 0.5f);
-                if (yhat) z = csub(z, yhat[blk(b, n, nh)]);
+                const float2 z = csub(cscale(cadd(xt[r], cconj(xb)), 0.5f), yh[r]);
                 zh[blk(b, n, nh)] = z;
                 acc[0] += 2.f * cabs2(z);
             }
@@ -223,7 +232,7 @@ __global__ __launch_bounds__(2 * NuCfg<K>::T) void k_nufft_fwd(const float2* __r
     }
     if (partials) {
         __syncthreads();
-        block_sum_store<2 * Cf::T, 1>(acc, reinterpret_cast<float*>(smem), partials + blockIdx.x * kRedSlots);
+        block_sum_store<2 * Cf::T, 1>(acc, reinterpret_cast<float*>(smem), partials + b * kRedSlots);
     }
 }
 
@@ -249,13 +258,25 @@ __global__ __launch_bounds__(NuAdjCfg<K>::T) void k_nufft_adj(const float2* __re
     float2* Y = smem + kWtabEntries;                                  // Y'[g], then the FFT tile
     float2* SL = reinterpret_cast<float2*>(reinterpret_cast<char*>(Y) + Cf::YBUF);   // [SLOTC][3]
     const int tid = threadIdx.x;
-    const int col = blockIdx.x;
+    // Column order 0, 1, nx-1, 2, nx-2, ..., nx/2 placed XCD by XCD: both columns of a
+    // half-spectrum row and the neighbouring rows (which share cache lines in the blocked
+    // layout) are read through one XCD's L2.
+    const int pos = xcd_tile(blockIdx.x, gridDim.x);
+    const int col = pos == 0 ? 0 : (pos == a.nx - 1 ? a.nx / 2 : ((pos & 1) ? (pos + 1) / 2 : a.nx - pos / 2));
     const int row = col <= a.nx / 2 ? col : a.nx - col;
     const bool conj_in = col > a.nx / 2;
     for (int i = tid; i < kWtabEntries; i += T) wt[i] = a.wtab[i];
     for (int i = tid; i < K; i += T) Y[i] = c2(0.f, 0.f);
     const double q2 = a.q2[col];
     const float Bl = a.Bl[col];
+    // residual spectrum and modulation of the thread's samples, fetched up front
+    float2 xr[Cf::NCH], en[Cf::NCH];
+#pragma unroll
+    for (int ch = 0; ch < Cf::NCH; ++ch) {
+        const int n = min(ch * Cf::CS + tid, a.nk - 1);
+        xr[ch] = rh[blk(row, n, a.nx / 2 + 1)];
+        en[ch] = a.En[n];
+    }
     for (int ch = 0; ch < Cf::NCH; ++ch) {
         const int n = ch * Cf::CS + tid;
         const bool mine = tid < Cf::CS;
@@ -265,9 +286,8 @@ __global__ __launch_bounds__(NuAdjCfg<K>::T) void k_nufft_adj(const float2* __re
         const bool prop = mine && stolt_point(a, q2, n, t, fl, tau);
         float2 vn = c2(0.f, 0.f);
         if (prop) {
-            float2 x = rh[blk(row, n, a.nx / 2 + 1)];
-            if (conj_in) x = cconj(x);
-            vn = cmulc(x, modulation(a, Bl, n, t));
+            const float2 x = conj_in ? cconj(xr[ch]) : xr[ch];
+            vn = cmulc(x, modulation(a, en[ch], Bl, t));
         }
         // chunk base: smallest g0 among its propagating samples (g0 grows with n)
         int g0 = prop ? fl - kJ / 2 : 0x7fffffff;
