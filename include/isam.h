@@ -139,8 +139,9 @@ int isam_fista(isam_plan_t p, const float* y, float lambda, const float* w, int 
                void* stream);
 
 /* Per-pass timing (profiling support).  enable = 1 clears the accumulators and
- * makes every later operator / FISTA call on the plan record a HIP event pair
- * around each kernel pass on its stream; enable = 0 stops recording.  Elapsed
+ * makes every later operator / FISTA call on the plan attach a HIP event pair
+ * to each pass's kernel launch on its stream (the runtime stamps the pair with
+ * that kernel's own begin and end); enable = 0 stops recording.  Elapsed
  * times are summed when a call completes (calls that synchronise) or here.
  * ms_out[ISAM_NPASS] and count_out[ISAM_NPASS] (either may be NULL) receive
  * the summed milliseconds and launch counts per pass:

@@ -274,10 +274,10 @@ hipError_t launch_c2c(const float2* in, float2* out, int nk, const float2* tw, i
     const dim3 grid(nk / C);
     if (sign < 0) {
         set_lds(k_lat_c2c<N, C, -1, false, true>, Cf::LDS);
-        hipLaunchKernelGGL((k_lat_c2c<N, C, -1, false, true>), grid, dim3(Cf::T), Cf::LDS, s, in, out, nk, tw, scale);
+        ISAM_LAUNCH((k_lat_c2c<N, C, -1, false, true>), grid, dim3(Cf::T), Cf::LDS, s, in, out, nk, tw, scale);
     } else {
         set_lds(k_lat_c2c<N, C, +1, true, false>, Cf::LDS);
-        hipLaunchKernelGGL((k_lat_c2c<N, C, +1, true, false>), grid, dim3(Cf::T), Cf::LDS, s, in, out, nk, tw, scale);
+        ISAM_LAUNCH((k_lat_c2c<N, C, +1, true, false>), grid, dim3(Cf::T), Cf::LDS, s, in, out, nk, tw, scale);
     }
     return hipGetLastError();
 }
@@ -286,7 +286,7 @@ template <int N, int C>
 hipError_t launch_c2r(const float2* zh, float* sout, int nk, const float2* tw, hipStream_t s) {
     using Cf = LatCfg<N, C>;
     set_lds(k_lat_c2r<N, C>, Cf::LDS);
-    hipLaunchKernelGGL((k_lat_c2r<N, C>), dim3(nk / (2 * C)), dim3(Cf::T), Cf::LDS, s, zh, sout, nk, tw,
+    ISAM_LAUNCH((k_lat_c2r<N, C>), dim3(nk / (2 * C)), dim3(Cf::T), Cf::LDS, s, zh, sout, nk, tw,
                        1.0f / sqrtf((float)N));
     return hipGetLastError();
 }
@@ -295,7 +295,7 @@ template <int N, int C>
 hipError_t launch_r2c(const float* r, float2* rh, int nk, const float2* tw, hipStream_t s) {
     using Cf = LatCfg<N, C>;
     set_lds(k_lat_r2c<N, C>, Cf::LDS);
-    hipLaunchKernelGGL((k_lat_r2c<N, C>), dim3(nk / (2 * C)), dim3(Cf::T), Cf::LDS, s, r, rh, nk, tw,
+    ISAM_LAUNCH((k_lat_r2c<N, C>), dim3(nk / (2 * C)), dim3(Cf::T), Cf::LDS, s, r, rh, nk, tw,
                        1.0f / sqrtf((float)N));
     return hipGetLastError();
 }
@@ -308,11 +308,11 @@ hipError_t launch_fista(float2* eh, const float2* gh, float2* z, const float* w,
     const float scale = 1.0f / sqrtf((float)N);
     if (fs.norms) {
         set_lds(k_lat_fista<N, C, true>, Cf::LDS);
-        hipLaunchKernelGGL((k_lat_fista<N, C, true>), grid, dim3(Cf::T), Cf::LDS, s, eh, gh, z, w, nk, tw,
+        ISAM_LAUNCH((k_lat_fista<N, C, true>), grid, dim3(Cf::T), Cf::LDS, s, eh, gh, z, w, nk, tw,
                            scale, fs, partials);
     } else {
         set_lds(k_lat_fista<N, C, false>, Cf::LDS);
-        hipLaunchKernelGGL((k_lat_fista<N, C, false>), grid, dim3(Cf::T), Cf::LDS, s, eh, gh, z, w, nk, tw,
+        ISAM_LAUNCH((k_lat_fista<N, C, false>), grid, dim3(Cf::T), Cf::LDS, s, eh, gh, z, w, nk, tw,
                            scale, fs, partials);
     }
     return hipGetLastError();

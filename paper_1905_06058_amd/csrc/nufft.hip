@@ -361,7 +361,7 @@ hipError_t launch_fwd(const isam_plan_s* p, const float2* etahat, const float2* 
                       hipStream_t s) {
     using Cf = NuCfg<K>;
     set_lds(k_nufft_fwd<K>, Cf::LDS_FWD);
-    hipLaunchKernelGGL(k_nufft_fwd<K>, dim3(std::max(1, p->nx / 2)), dim3(2 * Cf::T), Cf::LDS_FWD, s, etahat,
+    ISAM_LAUNCH(k_nufft_fwd<K>, dim3(std::max(1, p->nx / 2)), dim3(2 * Cf::T), Cf::LDS_FWD, s, etahat,
                        yhat, zh, p->nufft_args(), partials);
     return hipGetLastError();
 }
@@ -370,7 +370,7 @@ template <int K>
 hipError_t launch_adj(const isam_plan_s* p, const float2* rh, float2* ghat, hipStream_t s) {
     using Cf = NuAdjCfg<K>;
     set_lds(k_nufft_adj<K>, Cf::LDS);
-    hipLaunchKernelGGL(k_nufft_adj<K>, dim3(p->nx), dim3(Cf::T), Cf::LDS, s, rh, ghat, p->nufft_args());
+    ISAM_LAUNCH(k_nufft_adj<K>, dim3(p->nx), dim3(Cf::T), Cf::LDS, s, rh, ghat, p->nufft_args());
     return hipGetLastError();
 }
 

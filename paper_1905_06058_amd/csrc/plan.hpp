@@ -1,9 +1,27 @@
 // Internal plan state shared by the ISAM library's translation units.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "isam.h"
+
+namespace isam {
+
+// Start/stop events the next pass kernel carries while isam_timing is on (set by the calling
+// thread around each timed pass, null otherwise).  The runtime stamps them with the kernel's own
+// begin and end, so a pass's time excludes the dispatch gaps around it.
+struct PassEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+extern thread_local PassEvents g_pass_events;
+
+}  // namespace isam
+
+// Launch of a pass kernel (hipLaunchKernelGGL plus the timing events of the pass, if any).
+#define ISAM_LAUNCH(KERNEL, GRID, BLOCK, LDS, S, ...)                                              \
+    hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, LDS, S, isam::g_pass_events.start, isam::g_pass_events.stop, \
+                          0u, __VA_ARGS__)
 
 namespace isam {
 

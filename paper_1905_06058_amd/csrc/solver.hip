@@ -14,6 +14,10 @@
 #include "common.hpp"
 #include "plan.hpp"
 
+namespace isam {
+thread_local PassEvents g_pass_events;
+}
+
 using namespace isam;
 
 namespace {
@@ -141,7 +145,8 @@ int sum_to_host(isam_plan_t p, const float* partials, int nblocks, int nslots, i
     return ISAM_OK;
 }
 
-// Per-pass timing: an event pair around each pass while isam_timing is enabled.
+// Per-pass timing: while isam_timing is enabled, each pass's kernel launch carries an event pair
+// that the runtime stamps with the kernel's begin and end.
 int tbegin(isam_plan_t p, int tag, hipStream_t s) {
     if (!p->timing_on) return -1;
     if (p->tev_used == p->tev_cap) {
@@ -168,13 +173,12 @@ int tbegin(isam_plan_t p, int tag, hipStream_t s) {
     p->tev_used++;
     p->ttag[i] = tag;
     p->tstream = s;
-    (void)hipEventRecord(p->tev[2 * i], s);
+    isam::g_pass_events.start = p->tev[2 * i];
+    isam::g_pass_events.stop = p->tev[2 * i + 1];
     return i;
 }
 
-void tend(isam_plan_t p, int i, hipStream_t s) {
-    if (i >= 0) (void)hipEventRecord(p->tev[2 * i + 1], s);
-}
+void tend(isam_plan_t, int, hipStream_t) { isam::g_pass_events = isam::PassEvents{}; }
 
 }  // namespace
 
