@@ -125,6 +125,19 @@ int isam_lipschitz(isam_plan_t p, int iters, uint64_t seed, const void* x0, doub
  * solves Eq. 12.  w may be NULL (w = 1).  Synchronises the stream. */
 int isam_lambda_max(isam_plan_t p, const float* y, const float* w, double* out, void* stream);
 
+/* Calibration gradient (Eq. 7 and 13 with the focal reference of the modulation c):
+ * grad_out[0..2] = d/d(a2, a3, z_focus) of sum_{p,n} g[p][n] (A eta)[p][n], evaluated
+ * at the plan's current calibration.  This is the calibration part of the
+ * vector-Jacobian product of isam_forward with cotangent g (the object part is
+ * isam_adjoint(g)).  With dc/dtheta = i D_theta c, D = ((k-k0)^2, (k-k0)^3, 2k - kz):
+ *   grad_theta = -sum_{l,n} D_theta Im(conj(G[l][n]) c X[l][n]),  G = lateral DFT of g.
+ * eta: device complex64 [nx][nk]; g: device float32 [nx][nk]; grad_out: host
+ * double[3], in units of 1/(rad m^-2), 1/(rad m^-3) and 1/m of the three parameters.
+ * Per-point terms are FP32, block sums FP32, the final sum FP64.  Synchronises the
+ * stream.  Errors: EINVAL (NULL argument), ENONFINITE. */
+int isam_calibration_grad(isam_plan_t p, const void* eta, const float* g, double* grad_out,
+                          void* stream);
+
 /* MBIR full-range ISAM by FISTA (Alg. 1) with step 1/L and threshold
  * lambda w_i / L (Eq. 14).  y: device float32 [nx][nk] measured spectra;
  * w: NULL or device float32 [nx][nk] (> 0); eta_out: device complex64

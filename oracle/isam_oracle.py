@@ -45,7 +45,8 @@ __all__ = [
     "modulation", "kb_scaling", "stolt_points", "minmax_system", "minmax_weights",
     "minmax_error", "forward", "adjoint", "forward_exact", "adjoint_exact",
     "forward_nufft", "adjoint_nufft", "soft_threshold", "lipschitz", "lambda_max",
-    "fista", "dense_matrix", "Operator",
+    "fista", "dense_matrix", "Operator", "resampled_spectrum", "calibration_derivatives",
+    "calibration_gradient",
 ]
 
 
@@ -412,6 +413,61 @@ def dense_matrix(g: Geometry, mode: str = "E") -> np.ndarray:
         e[i] = 1j
         M[:, 2 * i + 1] = op.A(e.reshape(g.nx, g.nk)).ravel()
     return M
+
+
+# --------------------------------------------------------------------------- calibration
+
+def resampled_spectrum(g: Geometry, eta: np.ndarray, mode: str = "N", columns=None, P=None) -> np.ndarray:
+    """X[l][n] = Nz^{-1/2} sum_m eta_hat[l][m] exp(+i kz[l][n] z_m), before the modulation c.
+
+    Mode E evaluates the sum directly (Eq. 3); mode N through the min-max NUFFT
+    (Eq. 16).  ``columns`` restricts the work to lateral frequencies on which
+    eta's lateral spectrum is supported (checked); X is zero elsewhere.
+    """
+    G = grids(g)
+    eta_hat = _lateral_fft(np.asarray(eta, np.complex128))
+    _check_support(eta_hat, columns, "resampled_spectrum")
+    cols = range(g.nx) if columns is None else sorted(set(columns))
+    kz, _ = axial_wavenumber(g)
+    tables = stolt_points(g) if mode == "N" else None
+    X = np.zeros((g.nx, g.nk), np.complex128)
+    for l in cols:
+        if mode == "E":
+            E = np.exp(1j * kz[l][:, None] * G.z[None, :])
+            X[l] = E @ eta_hat[l] / math.sqrt(g.nk)
+        elif mode == "N":
+            Pl = P[l] if P is not None else _interp_matrix(g, l, None, tables)
+            X[l] = Pl @ _oversampled_spectrum(g, eta_hat[l])[0] / math.sqrt(g.nk)
+        else:
+            raise ValueError(mode)
+    return X
+
+
+def calibration_derivatives(g: Geometry):
+    """D_theta with dc/dtheta = i D_theta c for theta = (a2, a3, z_focus).
+
+    From c = B e^{i phi} e^{i (2k - kz) z_f} and phi = a2 (k-k0)^2 + a3 (k-k0)^3
+    (Eq. 7, 13): D = ((k-k0)^2, (k-k0)^3, 2k - kz), each of shape (nx, nk).
+    """
+    G = grids(g)
+    kz, _ = axial_wavenumber(g)
+    d = np.broadcast_to((G.k - G.kc)[None, :], (g.nx, g.nk))
+    return d ** 2, d ** 3, 2 * G.k[None, :] - kz
+
+
+def calibration_gradient(g: Geometry, eta: np.ndarray, grad_s: np.ndarray, mode: str = "N",
+                         columns=None, P=None) -> np.ndarray:
+    """Gradient of <grad_s, A eta> with respect to theta = (a2, a3, z_focus).
+
+    A eta = Re(F^{-1}(c X)) with F the unitary lateral DFT; for real grad_s,
+    <grad_s, Re F^{-1} Y> = Re sum conj(F grad_s) Y, hence
+    d/dtheta = Re sum conj(F grad_s) (i D_theta c X).
+    """
+    X = resampled_spectrum(g, eta, mode, columns, P)
+    Gs = _lateral_fft(np.asarray(grad_s, np.float64).astype(np.complex128))
+    cX = modulation(g) * X
+    base = np.conj(Gs) * 1j * cX
+    return np.array([float(np.sum(np.real(base * D))) for D in calibration_derivatives(g)])
 
 
 # --------------------------------------------------------------------------- solver

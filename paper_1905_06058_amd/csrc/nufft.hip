@@ -236,6 +236,54 @@ __global__ __launch_bounds__(2 * NuCfg<K>::T) void k_nufft_fwd(const float2* __r
     }
 }
 
+// Calibration gradient (Eq. 7, 13).  With theta = (a2, a3, z_f) the modulation obeys
+// dc/dtheta = i D_theta c, D = ((k - k0)^2, (k - k0)^3, 2k - kz).  For real g and the unitary
+// lateral DFT, <g, Re F^{-1}(c X)> = Re sum_{l,n} conj(G[l][n]) c X[l][n] with G = F g, so
+//   d<g, A eta>/dtheta = -sum_{l,n} D_theta[l][n] Im(conj(G[l][n]) Xt[l][n]),   Xt = c X.
+// Same column pairing as k_nufft_fwd; each half accumulates its own column (G[nx - l] =
+// conj G[l] for real g) and the block writes three partial sums (slots 0..2).  ghalf is the
+// blocked half spectrum of g (rows 0..nx/2).
+template <int K>
+__global__ __launch_bounds__(2 * NuCfg<K>::T) void k_nufft_calgrad(const float2* __restrict__ etahat,
+                                                                   const float2* __restrict__ ghalf, NufftArgs a,
+                                                                   float* __restrict__ partials) {
+    using Cf = NuCfg<K>;
+    extern __shared__ float2 smem[];
+    const int half = threadIdx.x / Cf::T, tid = threadIdx.x % Cf::T;
+    float2* buf = smem + half * Cf::BUF;
+    float2* wt = smem + 2 * Cf::BUF;
+    for (int i = threadIdx.x; i < kWtabEntries; i += 2 * Cf::T) wt[i] = a.wtab[i];
+    const int b = blockIdx.x;
+    const int colB = b == 0 ? (a.nx >= 2 ? a.nx / 2 : -1) : a.nx - b;
+    const bool active = half == 0 || colB >= 0;
+    const int col = half == 0 ? b : (colB >= 0 ? colB : b);
+    float2 xt[Cf::NPT];
+    forward_column<K>(a, etahat, col, buf, wt, xt, tid);
+    const int nh = a.nx / 2 + 1;
+    const bool mirrored = col >= nh;
+    const int row = mirrored ? a.nx - col : col;
+    const double q2 = a.q2[col];
+    float acc[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int r = 0; r < Cf::NPT; ++r) {
+        const int n = tid + r * Cf::T;
+        if (!active || n >= a.nk) continue;
+        const double u = (double)(n - a.nk / 2) * a.dk;           // k - k0
+        const double k2 = 2.0 * (a.kc + u);
+        const double d = fma(k2, k2, -q2);
+        if (!(d > 0.0)) continue;                                  // evanescent: c = 0
+        float2 gl = ghalf[blk(row, n, nh)];
+        if (mirrored) gl = cconj(gl);
+        const float im = gl.x * xt[r].y - gl.y * xt[r].x;           // Im(conj(G) Xt)
+        const double dz = q2 / (k2 + sqrt(d));                      // 2k - kz without cancellation
+        acc[0] -= (float)(u * u) * im;
+        acc[1] -= (float)(u * u * u) * im;
+        acc[2] -= (float)dz * im;
+    }
+    __syncthreads();
+    block_sum_store<2 * Cf::T, 3>(acc, reinterpret_cast<float*>(smem), partials + b * kRedSlots);
+}
+
 // Transposed NUFFT of one column per block.  Column l reads the half-spectrum row
 // min(l, nx - l) of the real residual's lateral transform (conjugated above nx/2).
 //
@@ -367,6 +415,16 @@ hipError_t launch_fwd(const isam_plan_s* p, const float2* etahat, const float2* 
 }
 
 template <int K>
+hipError_t launch_calgrad(const isam_plan_s* p, const float2* etahat, const float2* ghalf, float* partials,
+                          hipStream_t s) {
+    using Cf = NuCfg<K>;
+    set_lds(k_nufft_calgrad<K>, Cf::LDS_FWD);
+    ISAM_LAUNCH(k_nufft_calgrad<K>, dim3(std::max(1, p->nx / 2)), dim3(2 * Cf::T), Cf::LDS_FWD, s, etahat, ghalf,
+                p->nufft_args(), partials);
+    return hipGetLastError();
+}
+
+template <int K>
 hipError_t launch_adj(const isam_plan_s* p, const float2* rh, float2* ghat, hipStream_t s) {
     using Cf = NuAdjCfg<K>;
     set_lds(k_nufft_adj<K>, Cf::LDS);
@@ -407,6 +465,11 @@ hipError_t launch_adj(const isam_plan_s* p, const float2* rh, float2* ghat, hipS
 hipError_t nufft_fwd(const isam_plan_s* p, const float2* etahat, const float2* yhat, float2* zh, float* partials,
                      hipStream_t s) {
     ISAM_K_SWITCH(p->K, return launch_fwd<K>(p, etahat, yhat, zh, partials, s));
+}
+
+hipError_t nufft_calgrad(const isam_plan_s* p, const float2* etahat, const float2* ghalf, float* partials,
+                         hipStream_t s) {
+    ISAM_K_SWITCH(p->K, return launch_calgrad<K>(p, etahat, ghalf, partials, s));
 }
 
 hipError_t nufft_adj(const isam_plan_s* p, const float2* rh, float2* ghat, hipStream_t s) {

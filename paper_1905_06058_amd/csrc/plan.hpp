@@ -126,6 +126,8 @@ hipError_t nufft_fwd(const isam_plan_s* p, const float2* etahat, const float2* y
                      hipStream_t s);
 int nufft_fwd_blocks(const isam_plan_s* p);
 hipError_t nufft_adj(const isam_plan_s* p, const float2* rh, float2* ghat, hipStream_t s);
+hipError_t nufft_calgrad(const isam_plan_s* p, const float2* etahat, const float2* ghalf, float* partials,
+                         hipStream_t s);
 int nufft_span_ok(const isam_plan_s* p);          // host check of the Stolt span bound
 
 }  // namespace isam

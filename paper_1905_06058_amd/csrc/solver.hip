@@ -306,6 +306,22 @@ extern "C" int isam_lambda_max(isam_plan_t p, const float* y, const float* w, do
     return std::isfinite(*out) ? ISAM_OK : ISAM_ENONFINITE;
 }
 
+extern "C" int isam_calibration_grad(isam_plan_t p, const void* eta, const float* g, double* grad_out,
+                                     void* stream) {
+    if (!p || !eta || !g || !grad_out) return ISAM_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (lat_c2c(p, (const float2*)eta, p->etahat, -1, s) != hipSuccess) return ISAM_EHIP;
+    if (lat_r2c(p, g, p->rh, s) != hipSuccess) return ISAM_EHIP;
+    if (nufft_calgrad(p, p->etahat, p->rh, p->red.partials, s) != hipSuccess) return ISAM_EHIP;
+    const int rc = sum_to_host(p, p->red.partials, nufft_fwd_blocks(p), 3, 0, s);
+    if (rc) return rc;
+    for (int i = 0; i < 3; ++i) {
+        grad_out[i] = p->host_sums[i];
+        if (!std::isfinite(grad_out[i])) return ISAM_ENONFINITE;
+    }
+    return ISAM_OK;
+}
+
 extern "C" int isam_fista(isam_plan_t p, const float* y, float lambda, const float* w, int max_iter,
                           float tol, double L, int add_residual, void* eta_out, isam_fista_info* info,
                           void* stream) {

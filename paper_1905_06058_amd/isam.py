@@ -26,7 +26,7 @@ ERRORS = {
 EXPORTS = (
     "isam_plan", "isam_set_calibration", "isam_forward", "isam_adjoint", "isam_normal",
     "isam_lipschitz", "isam_lambda_max", "isam_fista", "isam_destroy", "isam_strerror",
-    "isam_plan_dims", "isam_timing",
+    "isam_plan_dims", "isam_timing", "isam_calibration_grad",
 )
 
 PASS_NAMES = ("lateral_fft_fwd", "nufft_fwd", "lateral_c2r", "lateral_r2c", "nufft_adj",
@@ -94,6 +94,7 @@ def load_library() -> ctypes.CDLL:
         lib.isam_strerror.restype = ctypes.c_char_p
         lib.isam_plan_dims.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
         lib.isam_timing.argtypes = [vp, ctypes.c_int, ctypes.POINTER(dbl), ctypes.POINTER(ctypes.c_int64)]
+        lib.isam_calibration_grad.argtypes = [vp, vp, vp, ctypes.POINTER(dbl), vp]
         for name in EXPORTS:
             if name not in ("isam_destroy", "isam_strerror"):
                 getattr(lib, name).restype = ctypes.c_int
@@ -226,6 +227,15 @@ class Plan:
         _check(self._lib.isam_lambda_max(self._h, y.data_ptr(), wp, ctypes.byref(out), _stream(stream)),
                "isam_lambda_max")
         return out.value
+
+    def calibration_grad(self, eta: torch.Tensor, g: torch.Tensor, stream=None) -> tuple:
+        """d/d(a2, a3, z_focus) of sum(g * forward(eta)) at the current calibration."""
+        _dev_tensor(eta, torch.complex64, self.shape, "eta")
+        _dev_tensor(g, torch.float32, self.shape, "g")
+        out = (ctypes.c_double * 3)()
+        _check(self._lib.isam_calibration_grad(self._h, eta.data_ptr(), g.data_ptr(), out, _stream(stream)),
+               "isam_calibration_grad")
+        return (out[0], out[1], out[2])
 
     def fista(self, y: torch.Tensor, lam: float, iters: int, w: torch.Tensor | None = None,
               tol: float = 0.0, L: float = 0.0, add_residual: bool = False,

@@ -89,6 +89,7 @@ def test_entry_points_reject_null_plan(lib):
     assert lib.isam_lambda_max(None, buf, None, ctypes.byref(L), None) == -1
     assert lib.isam_fista(None, buf, 0.1, None, 1, 0.0, 1.0, 0, buf, None, None) == -1
     assert lib.isam_set_calibration(None, 0.0, 0.0, 0.0, None) == -1
+    assert lib.isam_calibration_grad(None, buf, buf, ctypes.byref(L), None) == -1
     assert lib.isam_plan_dims(None, None, None, None) == -1
     lib.isam_destroy(None)
 

@@ -251,6 +251,36 @@ def test_operator_norm_from_svd_and_power_iteration():
 
 # ------------------------------------------------------------------ prox and FISTA
 
+@pytest.mark.parametrize("mode", ["E", "N"])
+def test_calibration_gradient_matches_central_differences(mode):
+    """d<G, A_theta eta>/dtheta against FP64 central differences of the forward operator."""
+    g = tiny_geom(8, 64, edge_phase2=6 * math.pi, edge_phase3=2 * math.pi, focus_rows=9)
+    rng = np.random.default_rng(3)
+    eta = rand_obj(rng, g.nx, g.nk, clear_edge=False)
+    G = rng.standard_normal((g.nx, g.nk))
+    an = O.calibration_gradient(g, eta, G, mode)
+    for i, name in enumerate(("a2", "a3", "z_focus")):
+        v = getattr(g, name)
+        h = 1e-5 * abs(v)
+        fp = np.sum(G * O.forward(g.with_(**{name: v + h}), eta, mode))
+        fm = np.sum(G * O.forward(g.with_(**{name: v - h}), eta, mode))
+        assert abs(an[i] - (fp - fm) / (2 * h)) < 1e-6 * abs(an[i]), name
+
+
+def test_focus_does_not_act_on_a_single_ascan():
+    """With one A-scan only q = 0 exists, where the Stolt map is the identity (kz = 2k):
+    the focal depth changes nothing and its gradient vanishes."""
+    g = tiny_geom(1, 64, edge_phase2=6 * math.pi, focus_rows=9)
+    rng = np.random.default_rng(4)
+    eta = rand_obj(rng, 1, 64, clear_edge=False)
+    s0 = O.forward_exact(g, eta)
+    s1 = O.forward_exact(g.with_(z_focus=3 * g.z_focus), eta)
+    assert np.max(np.abs(s0 - s1)) < 1e-12 * np.max(np.abs(s0))
+    G = rng.standard_normal((1, 64))
+    grad = O.calibration_gradient(g, eta, G, "E")
+    assert grad[2] == 0.0 and grad[0] != 0.0
+
+
 def test_soft_threshold_closed_form_and_edges():
     """Eq. 14 equals u - theta u/|u| for |u| > theta and 0 otherwise; theta = 0 is the identity."""
     rng = np.random.default_rng(7)
