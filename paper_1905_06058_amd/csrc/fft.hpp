@@ -1,7 +1,8 @@
-// LDS-resident Stockham FFT for power-of-two lengths on CDNA4 wavefronts.
+// LDS-resident Stockham FFT on CDNA4 wavefronts for lengths N = Q 2^P, Q in {1, 3, 5, 7}.
 //
 // A tile of C independent length-N sequences lives in LDS with element (x, c)
-// at lds[lds_pad(x * LS + c)] (lds_size(N * LS) entries).  Passes use radices 2..16; the first and the last pass
+// at lds[lds_pad(x * LS + c)] (lds_size(N * LS) entries).  Passes use radices 2..16, plus
+// one radix-Q pass (second in the sequence) when N has the odd factor Q; the first and the last pass
 // share one "outer" radix RO so that the register layout a thread holds after
 // a transform (x = b + j N/RO for its butterflies b, j < RO) is exactly the
 // layout the first pass of the next transform expects.  That lets kernels
@@ -39,29 +40,42 @@ constexpr int fft_radix_log(int P, int pass, int L = 4) {
     const int rem = P - 2 * a - L * (pass - 1);
     return rem >= L ? L : rem;
 }
-constexpr int fft_stride_before(int P, int pass, int L = 4) {   // product of radices of passes < pass
-    return pass == 0 ? 1 : fft_stride_before(P, pass - 1, L) * (1 << fft_radix_log(P, pass - 1, L));
+// Lengths N = Q 2^P (Q odd): the power-of-two schedule above with one radix-Q pass
+// inserted after the first pass, so the first and last (outer) passes stay equal.
+// fft_stride: product of the radices before a pass; fft_stage_off: offset of a pass
+// (>= 1) in the staged twiddle table; fft_stage_len: the table's length.
+constexpr int fft_odd(int n) { return (n & 1) || n == 0 ? n : fft_odd(n >> 1); }
+constexpr int fft_p2(int n) { return ilog2(n / fft_odd(n)); }
+constexpr int fft_np(int N, int L = 4) { return fft_npass(fft_p2(N), L) + (fft_odd(N) > 1 ? 1 : 0); }
+constexpr int fft_radix(int N, int pass, int L = 4) {
+    return fft_odd(N) == 1 ? 1 << fft_radix_log(fft_p2(N), pass, L)
+           : pass == 0     ? 1 << fft_radix_log(fft_p2(N), 0, L)
+           : pass == 1     ? fft_odd(N)
+                           : 1 << fft_radix_log(fft_p2(N), pass - 1, L);
 }
-// Offset of pass `pass` (>= 1) in the staged twiddle table, and the table's length.
-constexpr int fft_stage_offset(int P, int pass, int L = 4) {
-    return pass <= 1 ? 0
-                     : fft_stage_offset(P, pass - 1, L) +
-                           (1 << fft_radix_log(P, pass - 1, L)) * fft_stride_before(P, pass - 1, L);
+constexpr int fft_stride(int N, int pass, int L = 4) {
+    return pass == 0 ? 1 : fft_stride(N, pass - 1, L) * fft_radix(N, pass - 1, L);
 }
-constexpr int fft_stage_size(int P, int L = 4) {
-    return fft_npass(P, L) <= 1 ? 1 : fft_stage_offset(P, fft_npass(P, L), L);
+constexpr int fft_stage_off(int N, int pass, int L = 4) {
+    return pass <= 1 ? 0 : fft_stage_off(N, pass - 1, L) + fft_radix(N, pass - 1, L) * fft_stride(N, pass - 1, L);
+}
+constexpr int fft_stage_len(int N, int L = 4) { return fft_np(N, L) <= 1 ? 1 : fft_stage_off(N, fft_np(N, L), L); }
+// Lengths the schedule supports: Q in {1, 3, 5, 7}, and with Q > 1 at least two
+// power-of-two passes (so that the outer passes exist).
+constexpr bool fft_length_ok(int N, int L = 4) {
+    return N >= 1 && (fft_odd(N) == 1 || ((fft_odd(N) == 3 || fft_odd(N) == 5 || fft_odd(N) == 7) &&
+                                          fft_npass(fft_p2(N), L) >= 2));
 }
 
-// Entry e of the staged table of a length-2^P transform: (exponent, period) of the
+// Entry e of the staged table of a length-N transform: (exponent, period) of the
 // twiddle exp(-2 pi i exponent / period) it holds.
-inline void fft_stage_entry(int P, int L, int e, int& expo, int& period) {
-    const int np = fft_npass(P, L);
+inline void fft_stage_entry(int N, int L, int e, int& expo, int& period) {
+    const int np = fft_np(N, L);
     for (int p = 1; p < np; ++p) {
-        const int R = 1 << fft_radix_log(P, p, L), NS = fft_stride_before(P, p, L);
-        const int off = fft_stage_offset(P, p, L);
+        const int R = fft_radix(N, p, L), NS = fft_stride(N, p, L);
+        const int off = fft_stage_off(N, p, L);
         if (e >= off && e < off + R * NS) {
-            const int j = (e - off) / NS, k = (e - off) % NS;
-            expo = j * k;
+            expo = ((e - off) / NS) * ((e - off) % NS);
             period = NS * R;
             return;
         }
@@ -145,6 +159,60 @@ struct Dft<4, SIGN> {
     }
 };
 
+// Odd radices R = 3, 5, 7: X_k = x_0 + sum_{n=1}^{H} (x_n + x_{R-n}) cos(2 pi n k / R)
+// + i SIGN sum_{n=1}^{H} (x_n - x_{R-n}) sin(2 pi n k / R), H = (R - 1) / 2, and X_{R-k} the
+// same with the sine part negated.  Tables hold cos / sin of 2 pi m / R, m < R.
+__device__ constexpr float kCos3[3] = {1.0f, -0.5f, -0.5f};
+__device__ constexpr float kSin3[3] = {0.0f, 0.86602540378443865f, -0.86602540378443865f};
+__device__ constexpr float kCos5[5] = {1.0f, 0.30901699437494742f, -0.80901699437494742f, -0.80901699437494742f,
+                                       0.30901699437494742f};
+__device__ constexpr float kSin5[5] = {0.0f, 0.95105651629515357f, 0.58778525229247313f, -0.58778525229247313f,
+                                       -0.95105651629515357f};
+__device__ constexpr float kCos7[7] = {1.0f, 0.62348980185873353f, -0.22252093395631440f, -0.90096886790241913f,
+                                       -0.90096886790241913f, -0.22252093395631440f, 0.62348980185873353f};
+__device__ constexpr float kSin7[7] = {0.0f, 0.78183148246802981f, 0.97492791218182361f, 0.43388373911755812f,
+                                       -0.43388373911755812f, -0.97492791218182361f, -0.78183148246802981f};
+template <int R>
+ISAM_DEV float odd_cos(int m) { return R == 3 ? kCos3[m] : R == 5 ? kCos5[m] : kCos7[m]; }
+template <int R>
+ISAM_DEV float odd_sin(int m) { return R == 3 ? kSin3[m] : R == 5 ? kSin5[m] : kSin7[m]; }
+
+template <int R, int SIGN>
+struct OddDft {
+    ISAM_DEV static void run(float2* x) {
+        constexpr int H = (R - 1) / 2;
+        float2 a[H], d[H];
+        float2 x0 = x[0], sum = x[0];
+#pragma unroll
+        for (int n = 1; n <= H; ++n) {
+            a[n - 1] = cadd(x[n], x[R - n]);
+            d[n - 1] = csub(x[n], x[R - n]);
+            sum = cadd(sum, a[n - 1]);
+        }
+#pragma unroll
+        for (int k = 1; k <= H; ++k) {
+            float2 re = x0, im = c2(0.f, 0.f);
+#pragma unroll
+            for (int n = 1; n <= H; ++n) {
+                const int m = (n * k) % R;
+                re = c2(fmaf(a[n - 1].x, odd_cos<R>(m), re.x), fmaf(a[n - 1].y, odd_cos<R>(m), re.y));
+                im = c2(fmaf(d[n - 1].x, odd_sin<R>(m), im.x), fmaf(d[n - 1].y, odd_sin<R>(m), im.y));
+            }
+            // i * SIGN * im
+            const float2 t = SIGN > 0 ? c2(-im.y, im.x) : c2(im.y, -im.x);
+            x[k] = cadd(re, t);
+            x[R - k] = csub(re, t);
+        }
+        x[0] = sum;
+    }
+};
+template <int SIGN>
+struct Dft<3, SIGN> : OddDft<3, SIGN> {};
+template <int SIGN>
+struct Dft<5, SIGN> : OddDft<5, SIGN> {};
+template <int SIGN>
+struct Dft<7, SIGN> : OddDft<7, SIGN> {};
+
 // Twiddle factor exp(SIGN * 2 pi i e / N) from the table of exp(-2 pi i e / N).
 template <int SIGN>
 ISAM_DEV float2 twiddle(const float2* tw, int e) {
@@ -154,9 +222,9 @@ ISAM_DEV float2 twiddle(const float2* tw, int e) {
 
 template <int N, int C, int T, int SIGN, int LS = C, int L = 4>
 struct LdsFft {
-    static constexpr int P = ilog2(N);
-    static constexpr int NP = fft_npass(P, L);
-    static constexpr int RO = 1 << fft_radix_log(P, 0, L);
+    static_assert(fft_length_ok(N, L), "unsupported transform length");
+    static constexpr int NP = fft_np(N, L);
+    static constexpr int RO = fft_radix(N, 0, L);
     static constexpr int NBO = N / RO * C;                  // butterflies in an outer pass
     static constexpr int BPTO = (NBO + T - 1) / T;          // per thread
     static constexpr int EPT = BPTO * RO;                   // register elements per thread
@@ -173,8 +241,8 @@ struct LdsFft {
     template <int PASS>
     ISAM_DEV static void middle(float2* lds, const float2* tw, int tid) {
         if constexpr (PASS < NP - 1) {
-            constexpr int R = 1 << fft_radix_log(P, PASS, L);
-            constexpr int NS = fft_stride_before(P, PASS, L);
+            constexpr int R = fft_radix(N, PASS, L);
+            constexpr int NS = fft_stride(N, PASS, L);
             constexpr int NB = N / R * C;
             constexpr int BPT = (NB + T - 1) / T;
             float2 x[BPT * R];
@@ -194,7 +262,7 @@ struct LdsFft {
                 if ((NB % T == 0) || f < NB) {
                     const int c = f % C, b = f / C;
                     const int k = b % NS;
-                    constexpr int OFF = fft_stage_offset(P, PASS, L);
+                    constexpr int OFF = fft_stage_off(N, PASS, L);
 #pragma unroll
                     for (int j = 1; j < R; ++j)
                         x[i * R + j] = cmul(x[i * R + j], twiddle<SIGN>(tw, OFF + j * NS + k));
@@ -247,7 +315,7 @@ struct LdsFft {
             for (int i = 0; i < BPTO; ++i) {
                 int c, b;
                 if (outer(tid, i, c, b)) {
-                    constexpr int OFF = fft_stage_offset(P, NP - 1, L);
+                    constexpr int OFF = fft_stage_off(N, NP - 1, L);
 #pragma unroll
                     for (int j = 1; j < RO; ++j) v[i * RO + j] = cmul(v[i * RO + j], twiddle<SIGN>(tw, OFF + j * SPAN + b));
                     Dft<RO, SIGN>::run(&v[i * RO]);

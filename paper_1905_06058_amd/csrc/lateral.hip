@@ -1,377 +1,28 @@
-// Lateral transforms of the ISAM operator: the unitary DFT over A-scans (F_<-> of
-// Eq. 2, 16, 17), applied to every depth row / wavenumber column.
-//
-// Data are [nx][nk] with the column (depth or k) index contiguous, so the
-// transform runs across rows at stride nk.  A workgroup owns a tile of C
-// consecutive complex columns (2C real columns for the real transforms) over all
-// nx rows: it reads C*8 contiguous bytes per row, transforms in LDS, writes back.
-// Real data use the two-for-one trick: real columns (2c, 2c+1) travel as one
-// complex lane, so a C2R/R2C pair costs what one complex transform costs.
-//
-// Kernels:
-//   k_lat_c2c    complex <-> complex, sign -1 (F_<->) or +1 (F_<->^{-1})
-//   k_lat_c2r    Hermitian half [nx/2+1][nk] -> real [nx][nk]   (Re of F^{-1}, Eq. 5)
-//   k_lat_r2c    real [nx][nk] -> Hermitian half                (F of a real residual)
-// Spectra (lateral-frequency side) and the FISTA state are column-blocked (blk); the
-// object and spectra at the C ABI are row-major.
-//   k_lat_fista  gradient step, soft threshold (Eq. 14), momentum (Alg. 1) and the
-//                forward lateral transform of the next momentum point, with Eq. 15 norms
-#include <algorithm>
-
-#include "common.hpp"
-#include "fft.hpp"
-#include "plan.hpp"
+// Lateral complex transforms (the lateral DFT of Eq. 2, 16, 17) and the lateral-length
+// dispatch shared by all lateral passes; the kernels are in lateral.hpp.
+#include "lateral.hpp"
 
 namespace isam {
-namespace {
 
-// Radix cap (log2) for a tile of C lanes of length N that should keep TT threads busy.
-constexpr int lat_pick_l(int P, int C, int TT) {
-    return ((1 << P) * C >> fft_radix_log(P, 0, 4)) >= TT   ? 4
-           : ((1 << P) * C >> fft_radix_log(P, 0, 3)) >= TT ? 3
-                                                             : 2;
-}
-
-template <int N, int C_, int TT = 512>
-struct LatCfg {
-    static constexpr int P = ilog2(N);
-    static constexpr int C = C_;                             // complex lanes per tile
-    static constexpr int L = lat_pick_l(P, C, TT);           // radix cap: keep TT threads busy
-    static constexpr int RO = 1 << fft_radix_log(P, 0, L);
-    static constexpr int NB = N / RO * C;
-    static constexpr int T = NB < 64 ? 64 : (NB > TT ? TT : NB);
-    static constexpr int SPAN = N / RO;
-    // the tile, and at least room for the block-reduction scratch (4 values x 8 waves)
-    static constexpr size_t LDS = (size_t)lds_size(N * C) * sizeof(float2) > 256 ? (size_t)lds_size(N * C) * sizeof(float2) : 256;
-    using Fwd = LdsFft<N, C, T, -1, C, L>;
-    using Inv = LdsFft<N, C, T, +1, C, L>;
-    static_assert(Fwd::EPT == Inv::EPT, "layouts");
-};
-
-// IB / OB: input / output in the column-blocked layout (else row-major [nx][nk]).
-template <int N, int C, int SIGN, bool IB, bool OB>
-__global__ __launch_bounds__((LatCfg<N, C>::T)) void k_lat_c2c(const float2* in, float2* out, int nk,
-                                                          const float2* __restrict__ tw, float scale) {
-    using Cf = LatCfg<N, C>;
-    using F = LdsFft<N, Cf::C, Cf::T, SIGN, Cf::C, Cf::L>;
-    extern __shared__ float2 lds[];
-    const int m0 = xcd_tile(blockIdx.x, gridDim.x) * Cf::C;
-    float2 v[F::EPT];
-#pragma unroll
-    for (int i = 0; i < F::BPTO; ++i) {
-        int c, b;
-        if (F::outer(threadIdx.x, i, c, b)) {
-#pragma unroll
-            for (int j = 0; j < Cf::RO; ++j)
-                v[i * Cf::RO + j] = in[IB ? blk(b + j * Cf::SPAN, m0 + c, N) : (unsigned)(b + j * Cf::SPAN) * nk + m0 + c];
-        }
-    }
-    F::run(v, lds, tw, threadIdx.x);
-#pragma unroll
-    for (int i = 0; i < F::BPTO; ++i) {
-        int c, b;
-        if (F::outer(threadIdx.x, i, c, b)) {
-#pragma unroll
-            for (int j = 0; j < Cf::RO; ++j)
-                out[OB ? blk(b + j * Cf::SPAN, m0 + c, N) : (unsigned)(b + j * Cf::SPAN) * nk + m0 + c] =
-                    cscale(v[i * Cf::RO + j], scale);
-        }
+bool lat_supported(int nx) {
+    switch (nx) {
+        case 1: case 2: case 4: case 8: case 16: case 32: case 64: case 128:
+        case 192: case 256: case 320: case 384: case 448: case 512: case 640: case 768:
+        case 896: case 1024: case 1280: case 1536: case 1792: case 2048:
+            return true;
+        default:
+            return false;
     }
 }
-
-// Two real columns (2c, 2c+1) of the C2R output as one complex lane: element x of the
-// lane is Za[x] + i Zb[x], with Z[x] = conj(Z[N - x]) above N/2 (Z column-blocked).
-template <int N>
-ISAM_DEV float2 hermitian_pair(const float2* zh, int x, int col) {
-    const int row = x <= N / 2 ? x : N - x;
-    const float4 z = *reinterpret_cast<const float4*>(zh + blk(row, col, N / 2 + 1));
-    return x <= N / 2 ? c2(z.x - z.w, z.y + z.z) : c2(z.x + z.w, z.z - z.y);
-}
-
-// Split the transform F of (ra + i rb) into the half spectra of ra and rb through LDS.
-template <int N, int T, int C, int L>
-ISAM_DEV void split_store(float2* lds, const float2 (&v)[LdsFft<N, C, T, -1, C, L>::EPT], float2* rh,
-                          int nk, int n0, float scale) {
-    using F = LdsFft<N, C, T, -1, C, L>;
-    constexpr int RO = F::RO, SPAN = F::SPAN;
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < F::BPTO; ++i) {
-        int c, b;
-        if (F::outer(threadIdx.x, i, c, b)) {
-#pragma unroll
-            for (int j = 0; j < RO; ++j) lds[lds_pad((b + j * SPAN) * C + c)] = v[i * RO + j];
-        }
-    }
-    __syncthreads();
-    const float h = 0.5f * scale;
-    for (int o = threadIdx.x; o < (N / 2 + 1) * C; o += T) {
-        const int l = o / C, c = o % C;
-        const float2 A = lds[lds_pad(l * C + c)];
-        const float2 B = cconj(lds[lds_pad(((N - l) & (N - 1)) * C + c)]);
-        const float2 s = cadd(A, B), d = csub(A, B);
-        *reinterpret_cast<float4*>(rh + blk(l, n0 + 2 * c, N / 2 + 1)) =
-            make_float4(s.x * h, s.y * h, d.y * h, -d.x * h);
-    }
-}
-
-template <int N, int C>
-__global__ __launch_bounds__((LatCfg<N, C>::T)) void k_lat_c2r(const float2* __restrict__ zh,
-                                                          float* __restrict__ s, int nk,
-                                                          const float2* __restrict__ tw, float scale) {
-    using Cf = LatCfg<N, C>;
-    using F = typename Cf::Inv;
-    extern __shared__ float2 lds[];
-    const int n0 = xcd_tile(blockIdx.x, gridDim.x) * 2 * Cf::C;
-    float2 v[F::EPT];
-#pragma unroll
-    for (int i = 0; i < F::BPTO; ++i) {
-        int c, b;
-        if (F::outer(threadIdx.x, i, c, b)) {
-#pragma unroll
-            for (int j = 0; j < Cf::RO; ++j)
-                v[i * Cf::RO + j] = hermitian_pair<N>(zh, b + j * Cf::SPAN, n0 + 2 * c);
-        }
-    }
-    F::run(v, lds, tw, threadIdx.x);
-#pragma unroll
-    for (int i = 0; i < F::BPTO; ++i) {
-        int c, b;
-        if (F::outer(threadIdx.x, i, c, b)) {
-#pragma unroll
-            for (int j = 0; j < Cf::RO; ++j)
-                *reinterpret_cast<float2*>(s + (unsigned)(b + j * Cf::SPAN) * nk + n0 + 2 * c) =
-                    cscale(v[i * Cf::RO + j], scale);
-        }
-    }
-}
-
-template <int N, int C>
-__global__ __launch_bounds__((LatCfg<N, C>::T)) void k_lat_r2c(const float* __restrict__ r,
-                                                          float2* __restrict__ rh, int nk,
-                                                          const float2* __restrict__ tw, float scale) {
-    using Cf = LatCfg<N, C>;
-    using F = typename Cf::Fwd;
-    extern __shared__ float2 lds[];
-    const int n0 = xcd_tile(blockIdx.x, gridDim.x) * 2 * Cf::C;
-    float2 v[F::EPT];
-#pragma unroll
-    for (int i = 0; i < F::BPTO; ++i) {
-        int c, b;
-        if (F::outer(threadIdx.x, i, c, b)) {
-#pragma unroll
-            for (int j = 0; j < Cf::RO; ++j)
-                v[i * Cf::RO + j] =
-                    *reinterpret_cast<const float2*>(r + (unsigned)(b + j * Cf::SPAN) * nk + n0 + 2 * c);
-        }
-    }
-    F::run(v, lds, tw, threadIdx.x);
-    split_store<N, Cf::T, Cf::C, Cf::L>(lds, v, rh, nk, n0, scale);
-}
-
-// Weighted complex soft threshold of Eq. 14 with threshold theta (theta = 0: identity).
-ISAM_DEV float2 soft_threshold(float2 u, float theta) {
-    const float mag = sqrtf(u.x * u.x + u.y * u.y);
-    const float sh = fmaxf(mag - theta, 0.f);
-    const float f = theta > 0.f ? sh / (sh + theta) : 1.f;
-    return cscale(u, f);
-}
-
-template <int N, int C, bool NORMS>
-__global__ __launch_bounds__((LatCfg<N, C>::T)) void k_lat_fista(float2* __restrict__ eta_hat,
-                                                            const float2* __restrict__ ghat,
-                                                            float2* __restrict__ z,
-                                                            const float* __restrict__ w, int nk,
-                                                            const float2* __restrict__ tw, float scale,
-                                                            FistaStep fs, float* __restrict__ partials) {
-    using Cf = LatCfg<N, C>;
-    using FI = typename Cf::Inv;
-    using FF = typename Cf::Fwd;
-    constexpr int RO = Cf::RO, SPAN = Cf::SPAN;
-    extern __shared__ float2 lds[];
-    const int m0 = xcd_tile(blockIdx.x, gridDim.x) * Cf::C;
-    float2 v[FI::EPT];
-    float2 gv[NORMS ? FI::EPT : 1];
-#pragma unroll
-    for (int i = 0; i < FI::BPTO; ++i) {
-        int c, b;
-        if (FI::outer(threadIdx.x, i, c, b)) {
-#pragma unroll
-            for (int j = 0; j < RO; ++j) {
-                const size_t off = blk(b + j * SPAN, m0 + c, N);
-                const float2 g = cscale(ghat[off], fs.step);
-                v[i * RO + j] = csub(eta_hat[off], g);          // u_hat = eta_hat - step * g_hat
-                if constexpr (NORMS) gv[i * RO + j] = g;
-            }
-        }
-    }
-    // z^{k-1} (and w) are fetched before the inverse transform so their latency overlaps it
-    float2 zpv[FI::EPT];
-    float wv[FI::EPT];
-#pragma unroll
-    for (int i = 0; i < FI::BPTO; ++i) {
-        int c, b;
-        if (FI::outer(threadIdx.x, i, c, b)) {
-#pragma unroll
-            for (int j = 0; j < RO; ++j) {
-                const size_t off = blk(b + j * SPAN, m0 + c, N);
-                zpv[i * RO + j] = z[off];
-                wv[i * RO + j] = w ? w[off] : 1.f;
-            }
-        }
-    }
-    FI::run(v, lds, tw, threadIdx.x);
-    if constexpr (NORMS) FI::run(gv, lds, tw, threadIdx.x);
-    float acc[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int i = 0; i < FI::BPTO; ++i) {
-        int c, b;
-        if (FI::outer(threadIdx.x, i, c, b)) {
-#pragma unroll
-            for (int j = 0; j < RO; ++j) {
-                const size_t off = blk(b + j * SPAN, m0 + c, N);
-                const float2 u = cscale(v[i * RO + j], scale);
-                const float wt = wv[i * RO + j];
-                const float2 zn = soft_threshold(u, fs.lam * fs.step * wt);
-                const float2 zp = zpv[i * RO + j];
-                z[off] = zn;
-                if constexpr (NORMS) {
-                    const float2 g = cscale(gv[i * RO + j], scale);
-                    const float2 d = csub(zn, cadd(u, g));      // z - eta, eta = u + g
-                    acc[0] += cabs2(d);
-                    acc[1] += cabs2(g);
-                    acc[2] += cabs2(csub(zn, u));               // z - eta + g
-                }
-                acc[3] += wt * sqrtf(cabs2(zn));
-                v[i * RO + j] = cadd(zn, cscale(csub(zn, zp), fs.beta));   // next momentum point
-            }
-        }
-    }
-    FF::run(v, lds, tw, threadIdx.x);
-#pragma unroll
-    for (int i = 0; i < FF::BPTO; ++i) {
-        int c, b;
-        if (FF::outer(threadIdx.x, i, c, b)) {
-#pragma unroll
-            for (int j = 0; j < RO; ++j)
-                eta_hat[blk(b + j * SPAN, m0 + c, N)] = cscale(v[i * RO + j], scale);
-        }
-    }
-    __syncthreads();
-    block_sum_store<Cf::T, 4>(acc, reinterpret_cast<float*>(lds), partials + blockIdx.x * kRedSlots);
-}
-
-template <typename K>
-void set_lds(K kern, size_t bytes) {
-    if (bytes > 65536) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-}
-
-// sign -1: row-major object -> blocked lateral spectrum; sign +1: blocked -> row-major.
-template <int N, int C>
-hipError_t launch_c2c(const float2* in, float2* out, int nk, const float2* tw, int sign, hipStream_t s) {
-    using Cf = LatCfg<N, C>;
-    const float scale = 1.0f / sqrtf((float)N);
-    const dim3 grid(nk / C);
-    if (sign < 0) {
-        set_lds(k_lat_c2c<N, C, -1, false, true>, Cf::LDS);
-        ISAM_LAUNCH((k_lat_c2c<N, C, -1, false, true>), grid, dim3(Cf::T), Cf::LDS, s, in, out, nk, tw, scale);
-    } else {
-        set_lds(k_lat_c2c<N, C, +1, true, false>, Cf::LDS);
-        ISAM_LAUNCH((k_lat_c2c<N, C, +1, true, false>), grid, dim3(Cf::T), Cf::LDS, s, in, out, nk, tw, scale);
-    }
-    return hipGetLastError();
-}
-
-template <int N, int C>
-hipError_t launch_c2r(const float2* zh, float* sout, int nk, const float2* tw, hipStream_t s) {
-    using Cf = LatCfg<N, C>;
-    set_lds(k_lat_c2r<N, C>, Cf::LDS);
-    ISAM_LAUNCH((k_lat_c2r<N, C>), dim3(nk / (2 * C)), dim3(Cf::T), Cf::LDS, s, zh, sout, nk, tw,
-                       1.0f / sqrtf((float)N));
-    return hipGetLastError();
-}
-
-template <int N, int C>
-hipError_t launch_r2c(const float* r, float2* rh, int nk, const float2* tw, hipStream_t s) {
-    using Cf = LatCfg<N, C>;
-    set_lds(k_lat_r2c<N, C>, Cf::LDS);
-    ISAM_LAUNCH((k_lat_r2c<N, C>), dim3(nk / (2 * C)), dim3(Cf::T), Cf::LDS, s, r, rh, nk, tw,
-                       1.0f / sqrtf((float)N));
-    return hipGetLastError();
-}
-
-template <int N, int C>
-hipError_t launch_fista(float2* eh, const float2* gh, float2* z, const float* w, int nk, const float2* tw,
-                        FistaStep fs, float* partials, hipStream_t s) {
-    using Cf = LatCfg<N, C>;
-    const dim3 grid(nk / C);
-    const float scale = 1.0f / sqrtf((float)N);
-    if (fs.norms) {
-        set_lds(k_lat_fista<N, C, true>, Cf::LDS);
-        ISAM_LAUNCH((k_lat_fista<N, C, true>), grid, dim3(Cf::T), Cf::LDS, s, eh, gh, z, w, nk, tw,
-                           scale, fs, partials);
-    } else {
-        set_lds(k_lat_fista<N, C, false>, Cf::LDS);
-        ISAM_LAUNCH((k_lat_fista<N, C, false>), grid, dim3(Cf::T), Cf::LDS, s, eh, gh, z, w, nk, tw,
-                           scale, fs, partials);
-    }
-    return hipGetLastError();
-}
-
-}  // namespace
-
-// Tile widths built per lateral length: C complex lanes per tile (2C real columns for the
-// real transforms).  Small transforms use 8 lanes; from 256 A-scans up the plan picks one
-// of {1, 2, 4, 8} (tunable).  The defaults, 8 lanes for complex passes and 4 for real ones,
-// make a tile one 8-column block of the blocked layout: one contiguous run of memory.
-#define ISAM_LAT_C(SEL, DEF, CALL)                                     \
-    switch (SEL) {                                                     \
-        case 1: { constexpr int C = 1; CALL; }                         \
-        case 2: { constexpr int C = 2; CALL; }                         \
-        case 8: { constexpr int C = N >= 2048 ? 4 : 8; CALL; }         \
-        case 4: { constexpr int C = 4; CALL; }                         \
-        default: { constexpr int C = DEF; CALL; }                      \
-    }
-#define ISAM_LAT_SWITCH(CALL) ISAM_LAT_SWITCH_(p->lat_c, N >= 2048 ? 4 : 8, CALL)
-#define ISAM_LAT_SWITCH_R(CALL) ISAM_LAT_SWITCH_(p->lat_cr, 4, CALL)
-#define ISAM_LAT_SWITCH_(SEL, DEF, CALL)                               \
-    switch (p->nx) {                                                   \
-        case 1: { constexpr int N = 1, C = 8; CALL; }                  \
-        case 2: { constexpr int N = 2, C = 8; CALL; }                  \
-        case 4: { constexpr int N = 4, C = 8; CALL; }                  \
-        case 8: { constexpr int N = 8, C = 8; CALL; }                  \
-        case 16: { constexpr int N = 16, C = 8; CALL; }                \
-        case 32: { constexpr int N = 32, C = 8; CALL; }                \
-        case 64: { constexpr int N = 64, C = 8; CALL; }                \
-        case 128: { constexpr int N = 128, C = 8; CALL; }              \
-        case 256: { constexpr int N = 256; ISAM_LAT_C(SEL, DEF, CALL) }          \
-        case 512: { constexpr int N = 512; ISAM_LAT_C(SEL, DEF, CALL) }          \
-        case 1024: { constexpr int N = 1024; ISAM_LAT_C(SEL, DEF, CALL) }        \
-        case 2048: { constexpr int N = 2048; ISAM_LAT_C(SEL, DEF, CALL) }        \
-        default: return hipErrorInvalidValue;                          \
-    }
 
 // Radix cap (log2) of the lateral FFT in use: selects the matching staged twiddle table.
 int lat_l(const isam_plan_s* p) {
     ISAM_LAT_SWITCH(return (LatCfg<N, C>::L));
 }
-int lat_l_real(const isam_plan_s* p) {
-    ISAM_LAT_SWITCH_R(return (LatCfg<N, C>::L));
-}
-
 hipError_t lat_c2c(const isam_plan_s* p, const float2* in, float2* out, int sign, hipStream_t s) {
     ISAM_LAT_SWITCH(return (launch_c2c<N, C>(in, out, p->nk, p->twX[lat_l(p)], sign, s)));
 }
-hipError_t lat_c2r(const isam_plan_s* p, const float2* zh, float* sout, hipStream_t s) {
-    ISAM_LAT_SWITCH_R(return (launch_c2r<N, C>(zh, sout, p->nk, p->twX[lat_l_real(p)], s)));
-}
-hipError_t lat_r2c(const isam_plan_s* p, const float* r, float2* rh, hipStream_t s) {
-    ISAM_LAT_SWITCH_R(return (launch_r2c<N, C>(r, rh, p->nk, p->twX[lat_l_real(p)], s)));
-}
-hipError_t lat_fista(const isam_plan_s* p, float2* eh, const float2* gh, float2* z, const float* w,
-                     FistaStep fs, float* partials, hipStream_t s) {
-    ISAM_LAT_SWITCH(return (launch_fista<N, C>(eh, gh, z, w, p->nk, p->twX[lat_l(p)], fs, partials, s)));
-}
+
 int lat_blocks(const isam_plan_s* p, int kind) {
     if (kind == 0) {
         ISAM_LAT_SWITCH(return p->nk / C);

@@ -1,0 +1,19 @@
+// Lateral real transforms: C2R (real projection of Eq. 5) and R2C (lateral spectrum of real
+// spectra); the kernels are in lateral.hpp.
+#include "lateral.hpp"
+
+namespace isam {
+
+int lat_l_real(const isam_plan_s* p) {
+    ISAM_LAT_SWITCH_R(return (LatCfg<N, C>::L));
+}
+
+hipError_t lat_c2r(const isam_plan_s* p, const float2* zh, float* sout, hipStream_t s) {
+    ISAM_LAT_SWITCH_R(return (launch_c2r<N, C>(zh, sout, p->nk, p->twX[lat_l_real(p)], s)));
+}
+
+hipError_t lat_r2c(const isam_plan_s* p, const float* r, float2* rh, hipStream_t s) {
+    ISAM_LAT_SWITCH_R(return (launch_r2c<N, C>(r, rh, p->nk, p->twX[lat_l_real(p)], s)));
+}
+
+}  // namespace isam

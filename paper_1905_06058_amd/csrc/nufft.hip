@@ -31,8 +31,7 @@ namespace {
 template <int K>
 struct NuCfg {
     static constexpr int NK = K / 2;
-    static constexpr int P = ilog2(K);
-    static constexpr int RO = 1 << fft_radix_log(P, 0);
+    static constexpr int RO = fft_radix(K, 0);
     static constexpr int NB = K / RO;
     static constexpr int T = NB < 64 ? 64 : (NB > 256 ? 256 : NB);    // threads per column
     static constexpr int NPT = (NK + T - 1) / T;           // output samples per thread
@@ -49,9 +48,8 @@ struct NuCfg {
 template <int K>
 struct NuAdjCfg {
     static constexpr int NK = K / 2;
-    static constexpr int P = ilog2(K);
     static constexpr int L = 3;
-    static constexpr int RO = 1 << fft_radix_log(P, 0, L);
+    static constexpr int RO = fft_radix(K, 0, L);
     static constexpr int NB = K / RO;
     static constexpr int T = NB < 64 ? 64 : (NB > 512 ? 512 : NB);
     static constexpr int SPAN = K / RO;
@@ -178,6 +176,7 @@ __global__ __launch_bounds__(2 * NuCfg<K>::T) void k_nufft_fwd(const float2* __r
                                                                float2* __restrict__ zh, NufftArgs a,
                                                                float* __restrict__ partials) {
     using Cf = NuCfg<K>;
+    if (a.stop && *a.stop) return;                     // solver already stopped (uniform)
     extern __shared__ float2 smem[];
     const int half = threadIdx.x / Cf::T, tid = threadIdx.x % Cf::T;
     float2* buf = smem + half * Cf::BUF;
@@ -300,6 +299,7 @@ __global__ __launch_bounds__(NuAdjCfg<K>::T) void k_nufft_adj(const float2* __re
     using Cf = NuAdjCfg<K>;
     using F = typename Cf::Adj;
     constexpr int T = Cf::T;
+    if (a.stop && *a.stop) return;                     // solver already stopped (uniform)
     extern __shared__ float2 smem[];
     __shared__ int s_red[T / 64];
     float2* wt = smem;
@@ -406,11 +406,13 @@ void set_lds(Kern kern, size_t bytes) {
 
 template <int K>
 hipError_t launch_fwd(const isam_plan_s* p, const float2* etahat, const float2* yhat, float2* zh, float* partials,
-                      hipStream_t s) {
+                      hipStream_t s, const int* stop) {
     using Cf = NuCfg<K>;
     set_lds(k_nufft_fwd<K>, Cf::LDS_FWD);
+    NufftArgs a = p->nufft_args();
+    a.stop = stop;
     ISAM_LAUNCH(k_nufft_fwd<K>, dim3(std::max(1, p->nx / 2)), dim3(2 * Cf::T), Cf::LDS_FWD, s, etahat,
-                       yhat, zh, p->nufft_args(), partials);
+                       yhat, zh, a, partials);
     return hipGetLastError();
 }
 
@@ -425,10 +427,12 @@ hipError_t launch_calgrad(const isam_plan_s* p, const float2* etahat, const floa
 }
 
 template <int K>
-hipError_t launch_adj(const isam_plan_s* p, const float2* rh, float2* ghat, hipStream_t s) {
+hipError_t launch_adj(const isam_plan_s* p, const float2* rh, float2* ghat, hipStream_t s, const int* stop) {
     using Cf = NuAdjCfg<K>;
     set_lds(k_nufft_adj<K>, Cf::LDS);
-    ISAM_LAUNCH(k_nufft_adj<K>, dim3(p->nx), dim3(Cf::T), Cf::LDS, s, rh, ghat, p->nufft_args());
+    NufftArgs a = p->nufft_args();
+    a.stop = stop;
+    ISAM_LAUNCH(k_nufft_adj<K>, dim3(p->nx), dim3(Cf::T), Cf::LDS, s, rh, ghat, a);
     return hipGetLastError();
 }
 
@@ -463,8 +467,8 @@ hipError_t launch_adj(const isam_plan_s* p, const float2* rh, float2* ghat, hipS
     }
 
 hipError_t nufft_fwd(const isam_plan_s* p, const float2* etahat, const float2* yhat, float2* zh, float* partials,
-                     hipStream_t s) {
-    ISAM_K_SWITCH(p->K, return launch_fwd<K>(p, etahat, yhat, zh, partials, s));
+                     hipStream_t s, const int* stop) {
+    ISAM_K_SWITCH(p->K, return launch_fwd<K>(p, etahat, yhat, zh, partials, s, stop));
 }
 
 hipError_t nufft_calgrad(const isam_plan_s* p, const float2* etahat, const float2* ghalf, float* partials,
@@ -472,8 +476,8 @@ hipError_t nufft_calgrad(const isam_plan_s* p, const float2* etahat, const float
     ISAM_K_SWITCH(p->K, return launch_calgrad<K>(p, etahat, ghalf, partials, s));
 }
 
-hipError_t nufft_adj(const isam_plan_s* p, const float2* rh, float2* ghat, hipStream_t s) {
-    ISAM_K_SWITCH(p->K, return launch_adj<K>(p, rh, ghat, s));
+hipError_t nufft_adj(const isam_plan_s* p, const float2* rh, float2* ghat, hipStream_t s, const int* stop) {
+    ISAM_K_SWITCH(p->K, return launch_adj<K>(p, rh, ghat, s, stop));
 }
 
 // Host replica of the Stolt positions per column.  Two bounds keep the adjoint exact:

@@ -45,6 +45,15 @@ struct NufftArgs {
     const float2* wtab;     // [kPieces][kJ][4] cubic coefficients of the weights (focus-phased)
     const float2* tw;       // staged twiddles of the K-point FFT, radices up to 16
     const float2* tw8;      // staged twiddles of the K-point FFT, radices up to 8
+    const int* stop;        // solver stop flag (non-zero: return at once), or null
+};
+
+// Device-side state of the relative-residual stop rule (Eq. 15): iteration at which it
+// held (0: not yet), status (ISAM_ENONFINITE on non-finite norms), last r_r.
+struct StopState {
+    int iter;
+    int status;
+    double rel_res;
 };
 
 struct Reduce {
@@ -90,6 +99,8 @@ struct isam_plan_s {
     float2* zblk = nullptr;       // [nx][nk] blocked FISTA iterate z
     isam::Reduce red;
     double* host_sums = nullptr;  // pinned host copy of red.sums
+    isam::StopState* stop = nullptr;       // device stop-rule state of the solver
+    isam::StopState* host_stop = nullptr;  // pinned host copy
 
     // per-pass timing (isam_timing)
     int timing_on = 0;
@@ -114,6 +125,7 @@ hipError_t lat_r2c(const isam_plan_s* p, const float* r, float2* rh, hipStream_t
 struct FistaStep {
     float step, lam, beta;
     int norms;
+    const int* stop;     // solver stop flag (non-zero: return at once), or null
 };
 hipError_t lat_fista(const isam_plan_s* p, float2* eta_hat, const float2* ghat, float2* z,
                      const float* w, FistaStep fs, float* partials, hipStream_t st);
@@ -123,9 +135,13 @@ int lat_l(const isam_plan_s* p);                  // radix cap (log2) of the lat
 // Forward Stolt NUFFT: zh = Z (yhat null) or the residual spectrum Z - yhat; ||.||^2 partials
 // (Parseval weights) per workgroup into partials slot 0 if partials is non-null.
 hipError_t nufft_fwd(const isam_plan_s* p, const float2* etahat, const float2* yhat, float2* zh, float* partials,
-                     hipStream_t s);
+                     hipStream_t s, const int* stop = nullptr);
+// Whether a lateral length has built kernels (powers of two up to 2048 and 3, 5, 7 times
+// powers of two from 192 up to 1792).
+bool lat_supported(int nx);
 int nufft_fwd_blocks(const isam_plan_s* p);
-hipError_t nufft_adj(const isam_plan_s* p, const float2* rh, float2* ghat, hipStream_t s);
+hipError_t nufft_adj(const isam_plan_s* p, const float2* rh, float2* ghat, hipStream_t s,
+                     const int* stop = nullptr);
 hipError_t nufft_calgrad(const isam_plan_s* p, const float2* etahat, const float2* ghalf, float* partials,
                          hipStream_t s);
 int nufft_span_ok(const isam_plan_s* p);          // host check of the Stolt span bound

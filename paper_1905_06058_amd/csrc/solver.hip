@@ -47,6 +47,46 @@ __global__ __launch_bounds__(256) void k_finalize(const float* __restrict__ part
     }
 }
 
+// Relative-residual stop rule (Eq. 15) on the device.  Sums slots 0..2 of the update
+// pass's partials (||z - eta||^2, ||g||^2, ||z - eta + g||^2) in FP64 with a fixed-order
+// tree, forms r_r and records iteration k in st->iter once r_r < tol (or the status on a
+// non-finite norm).  Does nothing once a stop has been recorded.
+__global__ __launch_bounds__(256) void k_stop_check(const float* __restrict__ partials, int nblocks,
+                                                    isam::StopState* st, int k, float tol) {
+    if (st->iter) return;                              // uniform
+    __shared__ double sh[3][256];
+    const int tid = threadIdx.x;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int b = tid; b < nblocks; b += 256)
+        for (int i = 0; i < 3; ++i) acc[i] += partials[b * kRedSlots + i];
+    for (int i = 0; i < 3; ++i) sh[i][tid] = acc[i];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w)
+            for (int i = 0; i < 3; ++i) sh[i][tid] += sh[i][tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const double d = sh[0][0], g = sh[1][0], e = sh[2][0];
+        if (!isfinite(d) || !isfinite(g) || !isfinite(e)) {
+            st->status = ISAM_ENONFINITE;
+            st->iter = k;
+        } else {
+            const double rr = sqrt(d) / (fmax(sqrt(g), sqrt(e)) + 1e-12);
+            st->rel_res = rr;
+            if (rr < (double)tol) st->iter = k;
+        }
+    }
+}
+
+__global__ void k_stop_reset(isam::StopState* st) {
+    if (threadIdx.x == 0) {
+        st->iter = 0;
+        st->status = ISAM_OK;
+        st->rel_res = -1.0;
+    }
+}
+
 // Partial sum of |x|^2 (slot 0) over a complex vector; 256 threads per block.
 __global__ __launch_bounds__(256) void k_sumsq(const float2* __restrict__ x, size_t n,
                                                float* __restrict__ partials) {
@@ -353,28 +393,38 @@ extern "C" int isam_fista(isam_plan_t p, const float* y, float lambda, const flo
     fs.step = (float)(1.0 / L);
     fs.lam = lambda;
     fs.norms = tol > 0.f;
+    // With a tolerance, Eq. 15 is evaluated on the device after every update pass; once it
+    // holds, every later solver kernel returns at once, so the state stays that of the
+    // stopping iteration.  The host reads the stop state every kPoll iterations.
+    constexpr int kPoll = 16;
+    const int* stop = fs.norms ? &p->stop->iter : nullptr;
+    fs.stop = stop;
+    hipLaunchKernelGGL(k_stop_reset, dim3(1), dim3(64), 0, s, p->stop);
+    HIP_OK(hipGetLastError());
     double t = 1.0, rel_res = -1.0;
-    int k = 0, status = ISAM_OK;
-    for (k = 1; k <= max_iter; ++k) {
-        TIMED(1, nufft_fwd(p, p->fista_hat, p->yhat, p->rh, part_r, s));
-        TIMED(4, nufft_adj(p, p->rh, p->ghat, s));
+    int iters_run = max_iter, status = ISAM_OK;
+    for (int k = 1; k <= max_iter; ++k) {
+        TIMED(1, nufft_fwd(p, p->fista_hat, p->yhat, p->rh, part_r, s, stop));
+        TIMED(4, nufft_adj(p, p->rh, p->ghat, s, stop));
         const double t_next = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
         fs.beta = (float)((t - 1.0) / t_next);
         TIMED(6, lat_fista(p, p->fista_hat, p->ghat, z, wb, fs, part_f, s));
         if (fs.norms) {
-            const int rc = sum_to_host(p, part_f, fb, 4, 0, s);
-            if (rc) return rc;
-            const double* h = p->host_sums;
-            if (!std::isfinite(h[0]) || !std::isfinite(h[1]) || !std::isfinite(h[2])) {
-                status = ISAM_ENONFINITE;
-                break;
+            hipLaunchKernelGGL(k_stop_check, dim3(1), dim3(256), 0, s, part_f, fb, p->stop, k, tol);
+            HIP_OK(hipGetLastError());
+            if (k % kPoll == 0 || k == max_iter) {
+                HIP_OK(hipMemcpyAsync(p->host_stop, p->stop, sizeof(isam::StopState), hipMemcpyDeviceToHost, s));
+                HIP_OK(hipStreamSynchronize(s));
+                if (p->host_stop->iter) break;
             }
-            rel_res = std::sqrt(h[0]) / (std::max(std::sqrt(h[1]), std::sqrt(h[2])) + 1e-12);
-            if (rel_res < tol) break;
         }
         t = t_next;
     }
-    const int iters_run = std::min(k, max_iter);
+    if (fs.norms && max_iter > 0) {          // the last loop pass read the stop state
+        rel_res = p->host_stop->rel_res;
+        if (p->host_stop->iter) iters_run = p->host_stop->iter;
+        status = p->host_stop->status;
+    }
     double resid2 = 0.0, l1 = 0.0;
     if (max_iter > 0) {
         int rc = sum_to_host(p, part_r, rb, 1, 0, s);

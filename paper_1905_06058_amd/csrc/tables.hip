@@ -265,7 +265,7 @@ int validate(const isam_geometry* g) {
     if (!(g->dlambda < g->lambda_c)) return ISAM_EINVAL;
     if (g->ny != 1) return ISAM_EUNSUPPORTED;
     if (g->J != kJ || g->osf != 2) return ISAM_EUNSUPPORTED;
-    if (!is_pow2(g->nx) || g->nx > 2048) return ISAM_EUNSUPPORTED;
+    if (!lat_supported(g->nx)) return ISAM_EUNSUPPORTED;
     if (!is_pow2(g->nk) || g->nk > 4096) return ISAM_EUNSUPPORTED;
     const double beta = g->kb_beta > 0 ? g->kb_beta : 2.34 * g->J;
     if (!(beta > kPi * g->J / (2.0 * g->osf))) return ISAM_EINVAL;   // scaling defined on all rows
@@ -297,18 +297,17 @@ void derive(isam_plan_s* p, const isam_geometry* g) {
 
 int build_twiddles(isam_plan_s* p, hipStream_t s) {
     // staged tables: depth FFT (radix caps 16 and 8), lateral FFT (caps 4, 8, 16)
-    const int PK = ilog2(p->K), PX = ilog2(p->nx);
-    struct Item { int P, L; float2* dst; };
-    const Item items[] = {{PK, 4, p->twK}, {PK, 3, p->twK8}, {PX, 2, p->twX[2]}, {PX, 3, p->twX[3]},
-                          {PX, 4, p->twX[4]}};
+    struct Item { int N, L; float2* dst; };
+    const Item items[] = {{p->K, 4, p->twK}, {p->K, 3, p->twK8}, {p->nx, 2, p->twX[2]}, {p->nx, 3, p->twX[3]},
+                          {p->nx, 4, p->twX[4]}};
     int ntot = 0;
-    for (const Item& it : items) ntot += fft_stage_size(it.P, it.L);
+    for (const Item& it : items) ntot += fft_stage_len(it.N, it.L);
     int2* h = nullptr;
     if (hipHostMalloc((void**)&h, (size_t)ntot * sizeof(int2)) != hipSuccess) return ISAM_ENOMEM;
     int off = 0;
     for (const Item& it : items) {
-        const int n = fft_stage_size(it.P, it.L);
-        for (int e = 0; e < n; ++e) fft_stage_entry(it.P, it.L, e, h[off + e].x, h[off + e].y);
+        const int n = fft_stage_len(it.N, it.L);
+        for (int e = 0; e < n; ++e) fft_stage_entry(it.N, it.L, e, h[off + e].x, h[off + e].y);
         off += n;
     }
     int2* d = nullptr;
@@ -318,7 +317,7 @@ int build_twiddles(isam_plan_s* p, hipStream_t s) {
         rc = ISAM_EHIP;
     off = 0;
     for (const Item& it : items) {
-        const int n = fft_stage_size(it.P, it.L);
+        const int n = fft_stage_len(it.N, it.L);
         if (rc == ISAM_OK) {
             hipLaunchKernelGGL(k_twiddles, dim3((n + 255) / 256), dim3(256), 0, s, d + off, n, it.dst);
             if (hipGetLastError() != hipSuccess) rc = ISAM_EHIP;
@@ -388,6 +387,8 @@ void release(isam_plan_s* p) {
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     if (p->host_sums) (void)hipHostFree(p->host_sums);
+    if (p->stop) (void)hipFree(p->stop);
+    if (p->host_stop) (void)hipHostFree(p->host_stop);
     for (int i = 0; i < 2 * p->tev_cap; ++i)
         if (p->tev[i]) (void)hipEventDestroy(p->tev[i]);
     delete[] p->tev;
@@ -415,6 +416,7 @@ isam::NufftArgs isam_plan_s::nufft_args() const {
     a.wtab = wtab;
     a.tw = twK;
     a.tw8 = twK8;
+    a.stop = nullptr;
     return a;
 }
 
@@ -447,9 +449,9 @@ extern "C" int isam_plan(const isam_geometry* g, void* stream, isam_plan_t* out)
     rc = rc ? rc : dalloc(&p->En, p->nk);
     rc = rc ? rc : dalloc(&p->sm, p->nk);
     rc = rc ? rc : dalloc(&p->wtab, kWtabEntries);
-    rc = rc ? rc : dalloc(&p->twK, fft_stage_size(ilog2(p->K), 4));
-    rc = rc ? rc : dalloc(&p->twK8, fft_stage_size(ilog2(p->K), 3));
-    for (int L = 2; L <= 4; ++L) rc = rc ? rc : dalloc(&p->twX[L], fft_stage_size(ilog2(p->nx), L));
+    rc = rc ? rc : dalloc(&p->twK, fft_stage_len(p->K, 4));
+    rc = rc ? rc : dalloc(&p->twK8, fft_stage_len(p->K, 3));
+    for (int L = 2; L <= 4; ++L) rc = rc ? rc : dalloc(&p->twX[L], fft_stage_len(p->nx, L));
     rc = rc ? rc : dalloc(&p->wscratch, 2 * nsums);
     rc = rc ? rc : dalloc(&p->etahat, full);
     rc = rc ? rc : dalloc(&p->zh, half);
@@ -464,6 +466,9 @@ extern "C" int isam_plan(const isam_geometry* g, void* stream, isam_plan_t* out)
     rc = rc ? rc : dalloc(&p->red.partials, (size_t)p->red.maxBlocks * kRedSlots);
     rc = rc ? rc : dalloc(&p->red.sums, kRedSlots);
     if (rc == ISAM_OK && hipHostMalloc((void**)&p->host_sums, kRedSlots * sizeof(double)) != hipSuccess)
+        rc = ISAM_ENOMEM;
+    if (rc == ISAM_OK && hipMalloc((void**)&p->stop, sizeof(isam::StopState)) != hipSuccess) rc = ISAM_ENOMEM;
+    if (rc == ISAM_OK && hipHostMalloc((void**)&p->host_stop, sizeof(isam::StopState)) != hipSuccess)
         rc = ISAM_ENOMEM;
     hipStream_t s = (hipStream_t)stream;
     if (rc == ISAM_OK) rc = build_twiddles(p, s);

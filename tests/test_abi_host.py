@@ -59,7 +59,9 @@ def _plan_rc(lib, g):
     (dict(J=8), -3),
     (dict(osf=3), -3),
     (dict(nx=0), -1),
-    (dict(nx=96), -3),             # not a power of two
+    (dict(nx=96), -3),             # no lateral kernels built for this length
+    (dict(nx=576), -3),            # odd factor 9
+    (dict(nx=384), -5),            # 3 x 128: valid, but no device here
     (dict(nk=8192), -3),
     (dict(nx=4096), -3),
     (dict(ny=2), -3),

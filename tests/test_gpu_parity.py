@@ -56,6 +56,21 @@ def test_forward_adjoint_match_oracle(P, nx, nk):
     assert rel(a, O.adjoint_nufft(g, r)) < TOL_OP
 
 
+# lateral lengths with an odd factor (radix-3, -5, -7 passes)
+SIZES_MIXED = [(192, 64), (320, 32), (384, 32), (448, 16), (640, 16), (768, 16), (896, 16), (1536, 16)]
+
+
+@pytest.mark.parametrize("nx,nk", SIZES_MIXED)
+def test_mixed_radix_lateral_lengths(P, nx, nk):
+    o, eta, r = rand_case(nx, nk, seed=nx + nk)
+    g = O.Geometry.of(o)
+    with make_plan(P, o) as plan:
+        s = to_host(plan.forward(to_dev(eta)))
+        a = to_host(plan.adjoint(to_dev(r)))
+    assert rel(s, O.forward_nufft(g, eta)) < TOL_OP
+    assert rel(a, O.adjoint_nufft(g, r)) < TOL_OP
+
+
 @pytest.mark.parametrize("focus_rows", [0, -37, 13.25, 64.5])
 def test_focus_and_dispersion_variants(P, focus_rows):
     """Integer, negative and fractional focal rows (the fractional part takes the per-sample phase)."""
@@ -195,6 +210,42 @@ def test_fista_tiny_fixed_iterations(P):
     assert res.iters == 100 and res.status == 0
     assert rel(z, ref.z) < TOL_FISTA
     assert abs(res.resid2 - ref.resid2[-1]) < 1e-4 * ref.resid2[-1]
+
+
+def test_fista_device_stop_leaves_the_stopping_iterate(P):
+    """Eq. 15 is checked on the device every iteration; after it holds the solver kernels
+    return at once, so the image equals a fixed-count run of the reported length."""
+    w = ph.workload("tiny")
+    g = O.Geometry.of(w.optics)
+    y = ph.add_noise(O.Operator(g, "N").A(ph.phantom(w)), w.snr_db, w.seed)
+    with make_plan(P, w.optics) as plan:
+        L = plan.lipschitz(iters=50, seed=0)
+        lam = w.lam_frac * plan.lambda_max(to_dev(y))
+        a = plan.fista(to_dev(y), lam, 500, tol=2e-3, L=L)
+        za = to_host(a.eta)
+        b = plan.fista(to_dev(y), lam, a.iters, L=L)
+        zb = to_host(b.eta)
+    assert 0 < a.iters < 500 and a.iters % 16 != 0 and a.status == 0
+    assert 0 < a.rel_res < 2e-3
+    assert np.array_equal(za, zb)
+    assert a.resid2 == b.resid2
+
+
+def test_fista_mixed_radix_lateral_length(P):
+    """384 A-scans (3 x 128): the FISTA pass runs a radix-3 lateral transform."""
+    o = ph.custom_optics(384, 128, edge_phase2=20 * math.pi, edge_phase3=4 * math.pi, focus_rows=32)
+    g = O.Geometry.of(o)
+    rng = np.random.default_rng(17)
+    eta = ph.layers(rng, 384, 128, 2) + ph.point_scatterers(rng, 384, 128, 60)
+    op = O.Operator(g, "N")
+    y = ph.add_noise(op.A(eta), 25.0, 17)
+    with make_plan(P, o) as plan:
+        L = plan.lipschitz(iters=50, seed=0)
+        lam = 0.05 * plan.lambda_max(to_dev(y))
+        res = plan.fista(to_dev(y), lam, 40, L=L)
+        z = to_host(res.eta)
+    ref = O.fista(op, y, lam, L, 40)
+    assert rel(z, ref.z) < TOL_FISTA
 
 
 def test_fista_tiny_weighted_stop_and_residual(P):
