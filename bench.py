@@ -30,7 +30,7 @@ METRIC = "A^H·A op pairs/s + FISTA iter/s, 1024×2048 B-scan FP32 vs plain; %HB
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = ["paper_1905_06058_amd/csrc/" + f for f in
                   ("common.hpp", "fft.hpp", "plan.hpp", "lateral.hpp", "lateral.hip", "lateral_real.hip",
-                   "lateral_fista.hip", "nufft.hip", "solver.hip")]
+                   "lateral_fista.hip", "nufft.hip", "solver.hip", "batch.hip")]
 
 
 def parse():

@@ -166,6 +166,77 @@ int isam_fista(isam_plan_t p, const float* y, float lambda, const float* w, int 
 #define ISAM_NPASS 7
 int isam_timing(isam_plan_t p, int enable, double* ms_out, int64_t* count_out);
 
+/* ------------------------------------------------------------------------
+ * Batches of B-scans of uneven size.
+ *
+ * A batch holds one plan per scan (each with its own geometry: nx, nk, optics
+ * and calibration) and runs each pass of the operator (Eq. 5, 13, 16), its
+ * adjoint (Eq. 17) and the FISTA iteration (Alg. 1) as one launch per group of
+ * scans sharing a kernel specialisation (same nx for the lateral passes, same
+ * nk for the NUFFT passes) instead of one launch per scan.  One FISTA
+ * iteration is captured once in a hipGraph and replayed.
+ *
+ * Packed buffers: scan i occupies elements [off[i], off[i+1]) of every packed
+ * buffer (isam_batch_offsets), row-major [nx_i][nk_i] as for a single plan;
+ * objects are complex64, spectra float32.  All data pointers are caller-owned
+ * device memory; a batch may not run on two streams concurrently.
+ * ------------------------------------------------------------------------ */
+typedef struct isam_batch_s* isam_batch_t;
+
+/* Flag of isam_batch_fista: launch the iteration's kernels one by one instead of
+ * replaying the captured graph (same results, bit for bit). */
+#define ISAM_BATCH_NO_GRAPH 1
+
+/* Build a batch of nscans plans from geoms[0..nscans).  Errors: those of
+ * isam_plan for any scan (the batch is then not created), EINVAL, ENOMEM. */
+int isam_batch_plan(const isam_geometry* geoms, int nscans, void* stream, isam_batch_t* out);
+
+/* offsets[0..nscans] (host int64): element offsets of the scans in packed buffers. */
+int isam_batch_offsets(isam_batch_t b, int64_t* offsets);
+
+/* The plan of scan i (owned by the batch; valid until isam_batch_destroy).  Its
+ * single-scan calls use the same tables and tile widths as the batch. */
+int isam_batch_scan_plan(isam_batch_t b, int i, isam_plan_t* out);
+
+/* isam_set_calibration for scan i, keeping the batch's records in step. */
+int isam_batch_set_calibration(isam_batch_t b, int i, double a2, double a3, double z_focus,
+                               void* stream);
+
+/* Packed s = A eta per scan (isam_forward on every scan). */
+int isam_batch_forward(isam_batch_t b, const void* eta, float* s_out, void* stream);
+
+/* Packed eta = A^H r per scan (isam_adjoint on every scan). */
+int isam_batch_adjoint(isam_batch_t b, const float* r, void* eta_out, void* stream);
+
+/* FISTA on every scan (isam_fista per scan, all scans advancing together):
+ * lambda: host float[nscans]; L: host double[nscans] or NULL (entries <= 0 are
+ * computed by isam_lipschitz); w: packed weights or NULL; tol > 0 applies
+ * Eq. 15 per scan on the device (a scan that has stopped keeps its iterate;
+ * the loop ends when all have stopped or after max_iter iterations); info:
+ * host isam_fista_info[nscans] or NULL; flags: 0 or ISAM_BATCH_NO_GRAPH.
+ * Synchronises the stream.  Returns the first non-OK scan status, if any. */
+int isam_batch_fista(isam_batch_t b, const float* y, const float* lambda, const float* w,
+                     int max_iter, float tol, const double* L, int add_residual, int flags,
+                     void* eta_out, isam_fista_info* info, void* stream);
+
+/* Autotuner: for every group of scans with nx >= 192, times the batched update
+ * pass (complex tiles) and R2C pass (real tiles) at tile widths 2, 4 and 8
+ * lanes, `reps` launches each, and keeps the fastest.  Clobbers the scans'
+ * solver workspaces (not their tables); synchronises. */
+int isam_batch_tune(isam_batch_t b, int reps, void* stream);
+
+/* Tile widths in use: for up to cap lateral groups, nx and the lanes per tile of
+ * the complex and real passes; *ngroups receives the number of groups. */
+int isam_batch_tiles(isam_batch_t b, int32_t* nx, int32_t* sel_c, int32_t* sel_r, int32_t cap,
+                     int32_t* ngroups);
+
+/* Set the tile widths (lanes: 1, 2, 4 or 8) of the group with lateral length nx,
+ * e.g. from a saved tuning.  EINVAL if no group has that nx. */
+int isam_batch_set_tiles(isam_batch_t b, int32_t nx, int32_t sel_c, int32_t sel_r);
+
+/* Release a batch and its plans (NULL is allowed). */
+void isam_batch_destroy(isam_batch_t b);
+
 /* Release a plan (NULL is allowed). */
 void isam_destroy(isam_plan_t p);
 

@@ -3,8 +3,8 @@
 The computation lives in the HIP library ``libisam.so`` (C ABI in include/isam.h);
 this package is its Python binding.
 """
-from .isam import (EXPORTS, FistaInfo, FistaResult, Geometry, IsamError, LIB_PATH, Plan,  # noqa: F401
+from .isam import (EXPORTS, Batch, FistaInfo, FistaResult, Geometry, IsamError, LIB_PATH, Plan,  # noqa: F401
                    load_library)
 
-__all__ = ["Plan", "Geometry", "IsamError", "FistaResult", "FistaInfo", "load_library", "LIB_PATH",
+__all__ = ["Plan", "Batch", "Geometry", "IsamError", "FistaResult", "FistaInfo", "load_library", "LIB_PATH",
            "EXPORTS"]

@@ -30,4 +30,22 @@ int lat_blocks(const isam_plan_s* p, int kind) {
     ISAM_LAT_SWITCH_R(return p->nk / (2 * C));
 }
 
+int lat_tile(int nx, int sel, int real) {
+    if (real) {
+        ISAM_LAT_DISPATCH(nx, sel, ISAM_LAT_DEF_CR, return C);
+    }
+    ISAM_LAT_DISPATCH(nx, sel, ISAM_LAT_DEF_C, return C);
+}
+
+int lat_radix_cap(int nx, int sel, int real) {
+    if (real) {
+        ISAM_LAT_DISPATCH(nx, sel, ISAM_LAT_DEF_CR, return (LatCfg<N, C>::L));
+    }
+    ISAM_LAT_DISPATCH(nx, sel, ISAM_LAT_DEF_C, return (LatCfg<N, C>::L));
+}
+
+hipError_t lat_c2c_batch(int nx, int sel, const LatScan* recs, const int2* map, int nblk, int sign, hipStream_t s) {
+    ISAM_LAT_DISPATCH(nx, sel, ISAM_LAT_DEF_C, return (launch_c2c_batch<N, C>(recs, map, nblk, sign, s)));
+}
+
 }  // namespace isam

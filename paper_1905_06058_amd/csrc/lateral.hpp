@@ -50,12 +50,12 @@ struct LatCfg {
 
 // IB / OB: input / output in the column-blocked layout (else row-major [nx][nk]).
 template <int N, int C, int SIGN, bool IB, bool OB>
-__global__ __launch_bounds__((LatCfg<N, C>::T)) void k_lat_c2c(const float2* in, float2* out, int nk,
-                                                          const float2* __restrict__ tw, float scale) {
+ISAM_DEV void lat_c2c_body(const float2* in, float2* out, int nk, const float2* __restrict__ tw, float scale,
+                           int tile, int ntiles) {
     using Cf = LatCfg<N, C>;
     using F = LdsFft<N, Cf::C, Cf::T, SIGN, Cf::C, Cf::L>;
     extern __shared__ float2 lds[];
-    const int m0 = xcd_tile(blockIdx.x, gridDim.x) * Cf::C;
+    const int m0 = xcd_tile(tile, ntiles) * Cf::C;
     float2 v[F::EPT];
 #pragma unroll
     for (int i = 0; i < F::BPTO; ++i) {
@@ -77,6 +77,23 @@ __global__ __launch_bounds__((LatCfg<N, C>::T)) void k_lat_c2c(const float2* in,
                     cscale(v[i * Cf::RO + j], scale);
         }
     }
+}
+
+template <int N, int C, int SIGN, bool IB, bool OB>
+__global__ __launch_bounds__((LatCfg<N, C>::T)) void k_lat_c2c(const float2* in, float2* out, int nk,
+                                                          const float2* __restrict__ tw, float scale) {
+    lat_c2c_body<N, C, SIGN, IB, OB>(in, out, nk, tw, scale, blockIdx.x, gridDim.x);
+}
+
+// Batched: workgroup b runs tile map[b].y of scan map[b].x (all scans of one lateral length N).
+template <int N, int C, int SIGN, bool IB, bool OB>
+__global__ __launch_bounds__((LatCfg<N, C>::T)) void k_lat_c2c_batch(const LatScan* __restrict__ scans,
+                                                                const int2* __restrict__ map) {
+    const int2 m = map[blockIdx.x];
+    if (m.x < 0) return;                               // padding entry (uniform)
+    const LatScan& sc = scans[m.x];
+    lat_c2c_body<N, C, SIGN, IB, OB>(static_cast<const float2*>(sc.in), static_cast<float2*>(sc.out), sc.nk,
+                                     sc.tw, 1.0f / sqrtf((float)N), m.y, sc.ntiles);
 }
 
 // Two real columns (2c, 2c+1) of the C2R output as one complex lane: element x of the
@@ -116,13 +133,12 @@ ISAM_DEV void split_store(float2* lds, const float2 (&v)[LdsFft<N, C, T, -1, C, 
 }
 
 template <int N, int C>
-__global__ __launch_bounds__((LatCfg<N, C>::T)) void k_lat_c2r(const float2* __restrict__ zh,
-                                                          float* __restrict__ s, int nk,
-                                                          const float2* __restrict__ tw, float scale) {
+ISAM_DEV void lat_c2r_body(const float2* __restrict__ zh, float* __restrict__ s, int nk,
+                           const float2* __restrict__ tw, float scale, int tile, int ntiles) {
     using Cf = LatCfg<N, C>;
     using F = typename Cf::Inv;
     extern __shared__ float2 lds[];
-    const int n0 = xcd_tile(blockIdx.x, gridDim.x) * 2 * Cf::C;
+    const int n0 = xcd_tile(tile, ntiles) * 2 * Cf::C;
     float2 v[F::EPT];
 #pragma unroll
     for (int i = 0; i < F::BPTO; ++i) {
@@ -147,13 +163,29 @@ __global__ __launch_bounds__((LatCfg<N, C>::T)) void k_lat_c2r(const float2* __r
 }
 
 template <int N, int C>
-__global__ __launch_bounds__((LatCfg<N, C>::T)) void k_lat_r2c(const float* __restrict__ r,
-                                                          float2* __restrict__ rh, int nk,
+__global__ __launch_bounds__((LatCfg<N, C>::T)) void k_lat_c2r(const float2* __restrict__ zh,
+                                                          float* __restrict__ s, int nk,
                                                           const float2* __restrict__ tw, float scale) {
+    lat_c2r_body<N, C>(zh, s, nk, tw, scale, blockIdx.x, gridDim.x);
+}
+
+template <int N, int C>
+__global__ __launch_bounds__((LatCfg<N, C>::T)) void k_lat_c2r_batch(const LatScan* __restrict__ scans,
+                                                                const int2* __restrict__ map) {
+    const int2 m = map[blockIdx.x];
+    if (m.x < 0) return;                               // padding entry (uniform)
+    const LatScan& sc = scans[m.x];
+    lat_c2r_body<N, C>(static_cast<const float2*>(sc.in), static_cast<float*>(sc.out), sc.nk, sc.tw,
+                       1.0f / sqrtf((float)N), m.y, sc.ntiles);
+}
+
+template <int N, int C>
+ISAM_DEV void lat_r2c_body(const float* __restrict__ r, float2* __restrict__ rh, int nk,
+                           const float2* __restrict__ tw, float scale, int tile, int ntiles) {
     using Cf = LatCfg<N, C>;
     using F = typename Cf::Fwd;
     extern __shared__ float2 lds[];
-    const int n0 = xcd_tile(blockIdx.x, gridDim.x) * 2 * Cf::C;
+    const int n0 = xcd_tile(tile, ntiles) * 2 * Cf::C;
     float2 v[F::EPT];
 #pragma unroll
     for (int i = 0; i < F::BPTO; ++i) {
@@ -169,6 +201,23 @@ __global__ __launch_bounds__((LatCfg<N, C>::T)) void k_lat_r2c(const float* __re
     split_store<N, Cf::T, Cf::C, Cf::L>(lds, v, rh, nk, n0, scale);
 }
 
+template <int N, int C>
+__global__ __launch_bounds__((LatCfg<N, C>::T)) void k_lat_r2c(const float* __restrict__ r,
+                                                          float2* __restrict__ rh, int nk,
+                                                          const float2* __restrict__ tw, float scale) {
+    lat_r2c_body<N, C>(r, rh, nk, tw, scale, blockIdx.x, gridDim.x);
+}
+
+template <int N, int C>
+__global__ __launch_bounds__((LatCfg<N, C>::T)) void k_lat_r2c_batch(const LatScan* __restrict__ scans,
+                                                                const int2* __restrict__ map) {
+    const int2 m = map[blockIdx.x];
+    if (m.x < 0) return;                               // padding entry (uniform)
+    const LatScan& sc = scans[m.x];
+    lat_r2c_body<N, C>(static_cast<const float*>(sc.in), static_cast<float2*>(sc.out), sc.nk, sc.tw,
+                       1.0f / sqrtf((float)N), m.y, sc.ntiles);
+}
+
 // Weighted complex soft threshold of Eq. 14 with threshold theta (theta = 0: identity).
 ISAM_DEV float2 soft_threshold(float2 u, float theta) {
     const float mag = sqrtf(u.x * u.x + u.y * u.y);
@@ -178,19 +227,17 @@ ISAM_DEV float2 soft_threshold(float2 u, float theta) {
 }
 
 template <int N, int C, bool NORMS>
-__global__ __launch_bounds__((LatCfg<N, C>::T)) void k_lat_fista(float2* __restrict__ eta_hat,
-                                                            const float2* __restrict__ ghat,
-                                                            float2* __restrict__ z,
-                                                            const float* __restrict__ w, int nk,
-                                                            const float2* __restrict__ tw, float scale,
-                                                            FistaStep fs, float* __restrict__ partials) {
+ISAM_DEV void lat_fista_body(float2* __restrict__ eta_hat, const float2* __restrict__ ghat,
+                             float2* __restrict__ z, const float* __restrict__ w, int nk,
+                             const float2* __restrict__ tw, float scale, const FistaStep& fs,
+                             float* __restrict__ partials, int tile, int ntiles) {
     using Cf = LatCfg<N, C>;
     using FI = typename Cf::Inv;
     using FF = typename Cf::Fwd;
     constexpr int RO = Cf::RO, SPAN = Cf::SPAN;
     if (fs.stop && *fs.stop) return;                   // solver already stopped (uniform)
     extern __shared__ float2 lds[];
-    const int m0 = xcd_tile(blockIdx.x, gridDim.x) * Cf::C;
+    const int m0 = xcd_tile(tile, ntiles) * Cf::C;
     float2 v[FI::EPT];
     float2 gv[NORMS ? FI::EPT : 1];
 #pragma unroll
@@ -259,7 +306,32 @@ __global__ __launch_bounds__((LatCfg<N, C>::T)) void k_lat_fista(float2* __restr
         }
     }
     __syncthreads();
-    block_sum_store<Cf::T, 4>(acc, reinterpret_cast<float*>(lds), partials + blockIdx.x * kRedSlots);
+    block_sum_store<Cf::T, 4>(acc, reinterpret_cast<float*>(lds), partials + tile * kRedSlots);
+}
+
+template <int N, int C, bool NORMS>
+__global__ __launch_bounds__((LatCfg<N, C>::T)) void k_lat_fista(float2* __restrict__ eta_hat,
+                                                            const float2* __restrict__ ghat,
+                                                            float2* __restrict__ z,
+                                                            const float* __restrict__ w, int nk,
+                                                            const float2* __restrict__ tw, float scale,
+                                                            FistaStep fs, float* __restrict__ partials) {
+    lat_fista_body<N, C, NORMS>(eta_hat, ghat, z, w, nk, tw, scale, fs, partials, blockIdx.x, gridDim.x);
+}
+
+// Batched: the momentum weight of the iteration comes from the device (beta), the rest of
+// the step from each scan's record.
+template <int N, int C, bool NORMS>
+__global__ __launch_bounds__((LatCfg<N, C>::T)) void k_lat_fista_batch(const LatScan* __restrict__ scans,
+                                                                  const int2* __restrict__ map,
+                                                                  const float* __restrict__ beta) {
+    const int2 m = map[blockIdx.x];
+    if (m.x < 0) return;                               // padding entry (uniform)
+    const LatScan& sc = scans[m.x];
+    FistaStep fs = sc.fs;
+    fs.beta = *beta;
+    lat_fista_body<N, C, NORMS>(static_cast<float2*>(sc.out), static_cast<const float2*>(sc.in), sc.z, sc.w, sc.nk,
+                                sc.tw, 1.0f / sqrtf((float)N), fs, sc.partials, m.y, sc.ntiles);
 }
 
 template <typename K>
@@ -319,6 +391,51 @@ hipError_t launch_fista(float2* eh, const float2* gh, float2* z, const float* w,
     return hipGetLastError();
 }
 
+// Batched launchers: nblk workgroups over the block map of one group of scans.  Plain
+// launches (no timing events), so that they can be captured in a graph.
+template <int N, int C>
+hipError_t launch_c2c_batch(const LatScan* recs, const int2* map, int nblk, int sign, hipStream_t s) {
+    using Cf = LatCfg<N, C>;
+    if (sign < 0) {
+        set_lds(k_lat_c2c_batch<N, C, -1, false, true>, Cf::LDS);
+        hipLaunchKernelGGL((k_lat_c2c_batch<N, C, -1, false, true>), dim3(nblk), dim3(Cf::T), Cf::LDS, s, recs, map);
+    } else {
+        set_lds(k_lat_c2c_batch<N, C, +1, true, false>, Cf::LDS);
+        hipLaunchKernelGGL((k_lat_c2c_batch<N, C, +1, true, false>), dim3(nblk), dim3(Cf::T), Cf::LDS, s, recs, map);
+    }
+    return hipGetLastError();
+}
+
+template <int N, int C>
+hipError_t launch_c2r_batch(const LatScan* recs, const int2* map, int nblk, hipStream_t s) {
+    using Cf = LatCfg<N, C>;
+    set_lds(k_lat_c2r_batch<N, C>, Cf::LDS);
+    hipLaunchKernelGGL((k_lat_c2r_batch<N, C>), dim3(nblk), dim3(Cf::T), Cf::LDS, s, recs, map);
+    return hipGetLastError();
+}
+
+template <int N, int C>
+hipError_t launch_r2c_batch(const LatScan* recs, const int2* map, int nblk, hipStream_t s) {
+    using Cf = LatCfg<N, C>;
+    set_lds(k_lat_r2c_batch<N, C>, Cf::LDS);
+    hipLaunchKernelGGL((k_lat_r2c_batch<N, C>), dim3(nblk), dim3(Cf::T), Cf::LDS, s, recs, map);
+    return hipGetLastError();
+}
+
+template <int N, int C>
+hipError_t launch_fista_batch(int norms, const LatScan* recs, const int2* map, int nblk, const float* beta,
+                              hipStream_t s) {
+    using Cf = LatCfg<N, C>;
+    if (norms) {
+        set_lds(k_lat_fista_batch<N, C, true>, Cf::LDS);
+        hipLaunchKernelGGL((k_lat_fista_batch<N, C, true>), dim3(nblk), dim3(Cf::T), Cf::LDS, s, recs, map, beta);
+    } else {
+        set_lds(k_lat_fista_batch<N, C, false>, Cf::LDS);
+        hipLaunchKernelGGL((k_lat_fista_batch<N, C, false>), dim3(nblk), dim3(Cf::T), Cf::LDS, s, recs, map, beta);
+    }
+    return hipGetLastError();
+}
+
 }  // namespace
 
 // Tile widths built per lateral length: C complex lanes per tile (2C real columns for the
@@ -333,14 +450,16 @@ hipError_t launch_fista(float2* eh, const float2* gh, float2* z, const float* w,
         case 4: { constexpr int C = 4; CALL; }                         \
         default: { constexpr int C = DEF; CALL; }                      \
     }
-#define ISAM_LAT_SWITCH(CALL) ISAM_LAT_SWITCH_(p->lat_c, N >= 2048 ? 4 : 8, CALL)
-#define ISAM_LAT_SWITCH_R(CALL) ISAM_LAT_SWITCH_(p->lat_cr, 4, CALL)
+#define ISAM_LAT_SWITCH(CALL) ISAM_LAT_DISPATCH(p->nx, p->lat_c, ISAM_LAT_DEF_C, CALL)
+#define ISAM_LAT_SWITCH_R(CALL) ISAM_LAT_DISPATCH(p->nx, p->lat_cr, ISAM_LAT_DEF_CR, CALL)
+#define ISAM_LAT_DEF_C (N >= 2048 ? 4 : 8)
+#define ISAM_LAT_DEF_CR 4
 // Built lateral lengths: powers of two (up to 128 with fixed 8-lane tiles, above with a
 // tunable width) and 3, 5, 7 times powers of two from 192 to 1792.
 #define ISAM_LAT_S(NN, CALL) case NN: { constexpr int N = NN, C = 8; CALL; }
 #define ISAM_LAT_L(NN, SEL, DEF, CALL) case NN: { constexpr int N = NN; ISAM_LAT_C(SEL, DEF, CALL) }
-#define ISAM_LAT_SWITCH_(SEL, DEF, CALL)                                                     \
-    switch (p->nx) {                                                                         \
+#define ISAM_LAT_DISPATCH(NXV, SEL, DEF, CALL)                                               \
+    switch (NXV) {                                                                           \
         ISAM_LAT_S(1, CALL) ISAM_LAT_S(2, CALL) ISAM_LAT_S(4, CALL) ISAM_LAT_S(8, CALL)      \
         ISAM_LAT_S(16, CALL) ISAM_LAT_S(32, CALL) ISAM_LAT_S(64, CALL) ISAM_LAT_S(128, CALL) \
         ISAM_LAT_L(192, SEL, DEF, CALL) ISAM_LAT_L(256, SEL, DEF, CALL)                      \

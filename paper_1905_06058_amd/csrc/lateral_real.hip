@@ -16,4 +16,12 @@ hipError_t lat_r2c(const isam_plan_s* p, const float* r, float2* rh, hipStream_t
     ISAM_LAT_SWITCH_R(return (launch_r2c<N, C>(r, rh, p->nk, p->twX[lat_l_real(p)], s)));
 }
 
+hipError_t lat_c2r_batch(int nx, int sel, const LatScan* recs, const int2* map, int nblk, hipStream_t s) {
+    ISAM_LAT_DISPATCH(nx, sel, ISAM_LAT_DEF_CR, return (launch_c2r_batch<N, C>(recs, map, nblk, s)));
+}
+
+hipError_t lat_r2c_batch(int nx, int sel, const LatScan* recs, const int2* map, int nblk, hipStream_t s) {
+    ISAM_LAT_DISPATCH(nx, sel, ISAM_LAT_DEF_CR, return (launch_r2c_batch<N, C>(recs, map, nblk, s)));
+}
+
 }  // namespace isam

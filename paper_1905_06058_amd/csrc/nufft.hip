@@ -170,11 +170,12 @@ ISAM_DEV void forward_column(const NufftArgs& a, const float2* __restrict__ etah
 // F(Re F^{-1} X) is the Hermitian part Z of X, so the lateral transform of the residual
 // Re(F^{-1} X) - y needs no transform at all.  Partials of ||r||^2 = sum_l w_l |R_l|^2
 // (Parseval over the half spectrum, w = 1 at l = 0 and nx/2, else 2) go to partials.
+// Body of workgroup bidx of nblk (one scan); the kernels below run it for a single scan or
+// for the scans of a batch.
 template <int K>
-__global__ __launch_bounds__(2 * NuCfg<K>::T) void k_nufft_fwd(const float2* __restrict__ etahat,
-                                                               const float2* __restrict__ yhat,
-                                                               float2* __restrict__ zh, NufftArgs a,
-                                                               float* __restrict__ partials) {
+ISAM_DEV void nufft_fwd_body(const float2* __restrict__ etahat, const float2* __restrict__ yhat,
+                             float2* __restrict__ zh, const NufftArgs& a, float* __restrict__ partials, int bidx,
+                             int nblk) {
     using Cf = NuCfg<K>;
     if (a.stop && *a.stop) return;                     // solver already stopped (uniform)
     extern __shared__ float2 smem[];
@@ -182,7 +183,7 @@ __global__ __launch_bounds__(2 * NuCfg<K>::T) void k_nufft_fwd(const float2* __r
     float2* buf = smem + half * Cf::BUF;
     float2* wt = smem + 2 * Cf::BUF;
     for (int i = threadIdx.x; i < kWtabEntries; i += 2 * Cf::T) wt[i] = a.wtab[i];
-    const int b = xcd_tile(blockIdx.x, gridDim.x);     // neighbouring pairs on one XCD
+    const int b = xcd_tile(bidx, nblk);                // neighbouring pairs on one XCD
     const int colA = b;
     const int colB = b == 0 ? (a.nx >= 2 ? a.nx / 2 : -1) : a.nx - b;
     const int col = half == 0 ? colA : (colB >= 0 ? colB : colA);
@@ -233,6 +234,24 @@ __global__ __launch_bounds__(2 * NuCfg<K>::T) void k_nufft_fwd(const float2* __r
         __syncthreads();
         block_sum_store<2 * Cf::T, 1>(acc, reinterpret_cast<float*>(smem), partials + b * kRedSlots);
     }
+}
+
+template <int K>
+__global__ __launch_bounds__(2 * NuCfg<K>::T) void k_nufft_fwd(const float2* __restrict__ etahat,
+                                                               const float2* __restrict__ yhat,
+                                                               float2* __restrict__ zh, NufftArgs a,
+                                                               float* __restrict__ partials) {
+    nufft_fwd_body<K>(etahat, yhat, zh, a, partials, blockIdx.x, gridDim.x);
+}
+
+// Batched: workgroup b runs local workgroup map[b].y of scan map[b].x.
+template <int K>
+__global__ __launch_bounds__(2 * NuCfg<K>::T) void k_nufft_fwd_batch(const NuScan* __restrict__ scans,
+                                                                     const int2* __restrict__ map) {
+    const int2 m = map[blockIdx.x];
+    if (m.x < 0) return;                               // padding entry (uniform)
+    const NuScan& sc = scans[m.x];
+    nufft_fwd_body<K>(sc.in, sc.in2, sc.out, sc.a, sc.partials, m.y, sc.nblk);
 }
 
 // Calibration gradient (Eq. 7, 13).  With theta = (a2, a3, z_f) the modulation obeys
@@ -294,8 +313,8 @@ __global__ __launch_bounds__(2 * NuCfg<K>::T) void k_nufft_calgrad(const float2*
 // slot order) into Y'[cell mod K]; chunks follow one another, so every sum is formed in a
 // fixed order and the result is bitwise repeatable.
 template <int K>
-__global__ __launch_bounds__(NuAdjCfg<K>::T) void k_nufft_adj(const float2* __restrict__ rh,
-                                                              float2* __restrict__ ghat, NufftArgs a) {
+ISAM_DEV void nufft_adj_body(const float2* __restrict__ rh, float2* __restrict__ ghat, const NufftArgs& a,
+                             int bidx, int nblk) {
     using Cf = NuAdjCfg<K>;
     using F = typename Cf::Adj;
     constexpr int T = Cf::T;
@@ -309,7 +328,7 @@ __global__ __launch_bounds__(NuAdjCfg<K>::T) void k_nufft_adj(const float2* __re
     // Column order 0, 1, nx-1, 2, nx-2, ..., nx/2 placed XCD by XCD: both columns of a
     // half-spectrum row and the neighbouring rows (which share cache lines in the blocked
     // layout) are read through one XCD's L2.
-    const int pos = xcd_tile(blockIdx.x, gridDim.x);
+    const int pos = xcd_tile(bidx, nblk);
     const int col = pos == 0 ? 0 : (pos == a.nx - 1 ? a.nx / 2 : ((pos & 1) ? (pos + 1) / 2 : a.nx - pos / 2));
     const int row = col <= a.nx / 2 ? col : a.nx - col;
     const bool conj_in = col > a.nx / 2;
@@ -398,6 +417,21 @@ __global__ __launch_bounds__(NuAdjCfg<K>::T) void k_nufft_adj(const float2* __re
     }
 }
 
+template <int K>
+__global__ __launch_bounds__(NuAdjCfg<K>::T) void k_nufft_adj(const float2* __restrict__ rh,
+                                                              float2* __restrict__ ghat, NufftArgs a) {
+    nufft_adj_body<K>(rh, ghat, a, blockIdx.x, gridDim.x);
+}
+
+template <int K>
+__global__ __launch_bounds__(NuAdjCfg<K>::T) void k_nufft_adj_batch(const NuScan* __restrict__ scans,
+                                                                    const int2* __restrict__ map) {
+    const int2 m = map[blockIdx.x];
+    if (m.x < 0) return;                               // padding entry (uniform)
+    const NuScan& sc = scans[m.x];
+    nufft_adj_body<K>(sc.in, sc.out, sc.a, m.y, sc.nblk);
+}
+
 template <typename Kern>
 void set_lds(Kern kern, size_t bytes) {
     if (bytes > 65536)
@@ -478,6 +512,24 @@ hipError_t nufft_calgrad(const isam_plan_s* p, const float2* etahat, const float
 
 hipError_t nufft_adj(const isam_plan_s* p, const float2* rh, float2* ghat, hipStream_t s, const int* stop) {
     ISAM_K_SWITCH(p->K, return launch_adj<K>(p, rh, ghat, s, stop));
+}
+
+hipError_t nufft_fwd_batch(int K_, const NuScan* recs, const int2* map, int nblk, hipStream_t s) {
+    ISAM_K_SWITCH(K_, {
+        using Cf = NuCfg<K>;
+        set_lds(k_nufft_fwd_batch<K>, Cf::LDS_FWD);
+        hipLaunchKernelGGL(k_nufft_fwd_batch<K>, dim3(nblk), dim3(2 * Cf::T), Cf::LDS_FWD, s, recs, map);
+        return hipGetLastError();
+    });
+}
+
+hipError_t nufft_adj_batch(int K_, const NuScan* recs, const int2* map, int nblk, hipStream_t s) {
+    ISAM_K_SWITCH(K_, {
+        using Cf = NuAdjCfg<K>;
+        set_lds(k_nufft_adj_batch<K>, Cf::LDS);
+        hipLaunchKernelGGL(k_nufft_adj_batch<K>, dim3(nblk), dim3(Cf::T), Cf::LDS, s, recs, map);
+        return hipGetLastError();
+    });
 }
 
 // Host replica of the Stolt positions per column.  Two bounds keep the adjoint exact:

@@ -56,6 +56,42 @@ struct StopState {
     double rel_res;
 };
 
+// Step record of the FISTA update pass (Alg. 1, Eq. 14): step 1/L, lambda, momentum
+// weight beta, whether to form the Eq. 15 norms.
+struct FistaStep {
+    float step, lam, beta;
+    int norms;
+    const int* stop;     // solver stop flag (non-zero: return at once), or null
+};
+
+// Operands of one scan in a batched NUFFT pass (forward: in = eta_hat, in2 = F(y) or null,
+// out = Z or the residual spectrum, partials = ||r||^2 partials or null; adjoint: in =
+// residual half spectrum, out = g_hat).  nblk: the scan's workgroups in the pass.
+struct NuScan {
+    NufftArgs a;
+    const float2* in;
+    const float2* in2;
+    float2* out;
+    float* partials;
+    int nblk;
+};
+
+// Operands of one scan in a batched lateral pass.  c2c / c2r / r2c: in -> out.  FISTA
+// update: out = eta_hat (read and written), in = g_hat, z, w (or null), partials, and the
+// scan's step record fs (its beta is replaced by the batch's).  tw: the scan's lateral
+// twiddle table for the pass's radix cap; ntiles: the scan's workgroups in the pass.
+struct LatScan {
+    const void* in;
+    void* out;
+    float2* z;
+    const float* w;
+    float* partials;
+    const float2* tw;
+    FistaStep fs;
+    int nk;
+    int ntiles;
+};
+
 struct Reduce {
     float* partials;        // [maxBlocks][kRedSlots]
     double* sums;           // [kRedSlots] final FP64 values (device)
@@ -122,11 +158,6 @@ hipError_t lat_c2c(const isam_plan_s* p, const float2* in, float2* out, int sign
 hipError_t lat_c2r(const isam_plan_s* p, const float2* zh, float* s_out, hipStream_t st);
 hipError_t lat_r2c(const isam_plan_s* p, const float* r, float2* rh, hipStream_t st);
 // FISTA update pass; see solver.hip
-struct FistaStep {
-    float step, lam, beta;
-    int norms;
-    const int* stop;     // solver stop flag (non-zero: return at once), or null
-};
 hipError_t lat_fista(const isam_plan_s* p, float2* eta_hat, const float2* ghat, float2* z,
                      const float* w, FistaStep fs, float* partials, hipStream_t st);
 int lat_blocks(const isam_plan_s* p, int kind);   // number of workgroups of a lateral pass
@@ -136,6 +167,21 @@ int lat_l(const isam_plan_s* p);                  // radix cap (log2) of the lat
 // (Parseval weights) per workgroup into partials slot 0 if partials is non-null.
 hipError_t nufft_fwd(const isam_plan_s* p, const float2* etahat, const float2* yhat, float2* zh, float* partials,
                      hipStream_t s, const int* stop = nullptr);
+// Batched passes over one group of scans (same lateral length nx, or same depth FFT length
+// K).  recs: device records indexed by batch scan; map: device block map (scan, workgroup of
+// the scan) with nblk entries; sel: requested lateral tile width (lanes).
+hipError_t lat_c2c_batch(int nx, int sel, const LatScan* recs, const int2* map, int nblk, int sign, hipStream_t s);
+hipError_t lat_c2r_batch(int nx, int sel, const LatScan* recs, const int2* map, int nblk, hipStream_t s);
+hipError_t lat_r2c_batch(int nx, int sel, const LatScan* recs, const int2* map, int nblk, hipStream_t s);
+hipError_t lat_fista_batch(int nx, int sel, int norms, const LatScan* recs, const int2* map, int nblk,
+                           const float* beta, hipStream_t s);
+hipError_t nufft_fwd_batch(int K, const NuScan* recs, const int2* map, int nblk, hipStream_t s);
+hipError_t nufft_adj_batch(int K, const NuScan* recs, const int2* map, int nblk, hipStream_t s);
+int lat_tile(int nx, int sel, int real);        // lanes per tile built for (nx, sel)
+int lat_radix_cap(int nx, int sel, int real);   // radix cap (log2) of that configuration
+// FISTA set-up and output steps shared by the single and batched solvers (solver.hip).
+int fista_prepare(isam_plan_t p, const float* y, const float* w, hipStream_t s);
+int fista_finish(isam_plan_t p, double L, int add_residual, float2* out, hipStream_t s);
 // Whether a lateral length has built kernels (powers of two up to 2048 and 3, 5, 7 times
 // powers of two from 192 up to 1792).
 bool lat_supported(int nx);

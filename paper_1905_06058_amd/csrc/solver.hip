@@ -362,6 +362,40 @@ extern "C" int isam_calibration_grad(isam_plan_t p, const void* eta, const float
     return ISAM_OK;
 }
 
+namespace isam {
+
+// FISTA set-up (Alg. 1 with eta^1 = z^0 = 0): zero the state, bring the weights into the
+// blocked layout, and form the data's lateral spectrum yhat = F(y) (Hermitian half, blocked).
+int fista_prepare(isam_plan_t p, const float* y, const float* w, hipStream_t s) {
+    const size_t n = (size_t)p->nx * p->nk;
+    const int gb = grid_for(n);
+    if (nufft_fwd_blocks(p) + lat_blocks(p, 0) > p->red.maxBlocks) return ISAM_EUNSUPPORTED;
+    hipLaunchKernelGGL(k_zero, dim3(gb), dim3(256), 0, s, p->zblk, n);
+    hipLaunchKernelGGL(k_zero, dim3(gb), dim3(256), 0, s, p->fista_hat, n);
+    if (w) hipLaunchKernelGGL(k_to_blk_f, dim3(gb), dim3(256), 0, s, w, p->wbuf, p->nx, p->nk);
+    HIP_OK(hipGetLastError());
+    TIMED(3, lat_r2c(p, y, p->yhat, s));
+    return ISAM_OK;
+}
+
+// FISTA output: z^k in row-major order, plus the optional residual step of Alg. 1,
+// z += (1/L) A^H (y - A z).
+int fista_finish(isam_plan_t p, double L, int add_residual, float2* out, hipStream_t s) {
+    const size_t n = (size_t)p->nx * p->nk;
+    const int gb = grid_for(n);
+    hipLaunchKernelGGL(k_from_blk_c, dim3(gb), dim3(256), 0, s, p->zblk, out, p->nx, p->nk);
+    HIP_OK(hipGetLastError());
+    if (add_residual) {
+        int rc = normal_impl(p, out, p->yhat, p->vec, s);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_axpy, dim3(gb), dim3(256), 0, s, out, p->vec, (float)(1.0 / L), n);
+        HIP_OK(hipGetLastError());
+    }
+    return ISAM_OK;
+}
+
+}  // namespace isam
+
 extern "C" int isam_fista(isam_plan_t p, const float* y, float lambda, const float* w, int max_iter,
                           float tol, double L, int add_residual, void* eta_out, isam_fista_info* info,
                           void* stream) {
@@ -375,20 +409,15 @@ extern "C" int isam_fista(isam_plan_t p, const float* y, float lambda, const flo
         const int rc = isam_lipschitz(p, 50, 0, nullptr, &L, stream);
         if (rc) return rc;
     }
-    // FISTA state and weights in the column-blocked layout of the lateral passes; the data
-    // enter as their lateral spectrum yhat = F(y) (Hermitian half, blocked)
+    {
+        const int rc = isam::fista_prepare(p, y, w, s);
+        if (rc) return rc;
+    }
     float2* z = p->zblk;
     float* wb = w ? p->wbuf : nullptr;
-    const int gb = grid_for(n);
-    hipLaunchKernelGGL(k_zero, dim3(gb), dim3(256), 0, s, z, n);
-    hipLaunchKernelGGL(k_zero, dim3(gb), dim3(256), 0, s, p->fista_hat, n);
-    if (w) hipLaunchKernelGGL(k_to_blk_f, dim3(gb), dim3(256), 0, s, w, wb, p->nx, p->nk);
-    HIP_OK(hipGetLastError());
-    TIMED(3, lat_r2c(p, y, p->yhat, s));
     const int rb = nufft_fwd_blocks(p), fb = lat_blocks(p, 0);
     float* part_r = p->red.partials;                            // forward NUFFT, slot 0
     float* part_f = p->red.partials + (size_t)rb * kRedSlots;   // update pass, slots 0..3
-    if (rb + fb > p->red.maxBlocks) return ISAM_EUNSUPPORTED;
     FistaStep fs;
     fs.step = (float)(1.0 / L);
     fs.lam = lambda;
@@ -435,15 +464,9 @@ extern "C" int isam_fista(isam_plan_t p, const float* y, float lambda, const flo
         l1 = p->host_sums[3];
         if (!std::isfinite(resid2) || !std::isfinite(l1)) status = ISAM_ENONFINITE;
     }
-    float2* out = (float2*)eta_out;
-    hipLaunchKernelGGL(k_from_blk_c, dim3(gb), dim3(256), 0, s, z, out, p->nx, p->nk);
-    HIP_OK(hipGetLastError());
-    if (add_residual && status == ISAM_OK) {
-        // z += (1/L) A^H (y - A z)  ==  z -= (1/L) A^H (A z - y)
-        int rc = normal_impl(p, out, p->yhat, p->vec, s);
+    {
+        const int rc = isam::fista_finish(p, L, add_residual && status == ISAM_OK, (float2*)eta_out, s);
         if (rc) return rc;
-        hipLaunchKernelGGL(k_axpy, dim3(gb), dim3(256), 0, s, out, p->vec, (float)(1.0 / L), n);
-        HIP_OK(hipGetLastError());
     }
     HIP_OK(hipStreamSynchronize(s));
     isam_timing_collect(p);

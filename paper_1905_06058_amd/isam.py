@@ -27,7 +27,11 @@ EXPORTS = (
     "isam_plan", "isam_set_calibration", "isam_forward", "isam_adjoint", "isam_normal",
     "isam_lipschitz", "isam_lambda_max", "isam_fista", "isam_destroy", "isam_strerror",
     "isam_plan_dims", "isam_timing", "isam_calibration_grad",
+    "isam_batch_plan", "isam_batch_offsets", "isam_batch_scan_plan", "isam_batch_set_calibration",
+    "isam_batch_forward", "isam_batch_adjoint", "isam_batch_fista", "isam_batch_tune", "isam_batch_tiles",
+    "isam_batch_set_tiles", "isam_batch_destroy",
 )
+ISAM_BATCH_NO_GRAPH = 1
 
 PASS_NAMES = ("lateral_fft_fwd", "nufft_fwd", "lateral_c2r", "lateral_r2c", "nufft_adj",
               "lateral_fft_inv", "fista_update")
@@ -95,8 +99,23 @@ def load_library() -> ctypes.CDLL:
         lib.isam_plan_dims.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
         lib.isam_timing.argtypes = [vp, ctypes.c_int, ctypes.POINTER(dbl), ctypes.POINTER(ctypes.c_int64)]
         lib.isam_calibration_grad.argtypes = [vp, vp, vp, ctypes.POINTER(dbl), vp]
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        i32p = ctypes.POINTER(i32)
+        lib.isam_batch_plan.argtypes = [ctypes.POINTER(Geometry), ctypes.c_int, vp, ctypes.POINTER(vp)]
+        lib.isam_batch_offsets.argtypes = [vp, i64p]
+        lib.isam_batch_scan_plan.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp)]
+        lib.isam_batch_set_calibration.argtypes = [vp, ctypes.c_int, dbl, dbl, dbl, vp]
+        lib.isam_batch_forward.argtypes = [vp, vp, vp, vp]
+        lib.isam_batch_adjoint.argtypes = [vp, vp, vp, vp]
+        lib.isam_batch_fista.argtypes = [vp, vp, ctypes.POINTER(f32), vp, ctypes.c_int, f32, ctypes.POINTER(dbl),
+                                         ctypes.c_int, ctypes.c_int, vp, ctypes.POINTER(FistaInfo), vp]
+        lib.isam_batch_tune.argtypes = [vp, ctypes.c_int, vp]
+        lib.isam_batch_tiles.argtypes = [vp, i32p, i32p, i32p, i32, i32p]
+        lib.isam_batch_set_tiles.argtypes = [vp, i32, i32, i32]
+        lib.isam_batch_destroy.argtypes = [vp]
+        lib.isam_batch_destroy.restype = None
         for name in EXPORTS:
-            if name not in ("isam_destroy", "isam_strerror"):
+            if name not in ("isam_destroy", "isam_strerror", "isam_batch_destroy"):
                 getattr(lib, name).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -251,3 +270,122 @@ class Plan:
                                     ctypes.byref(info), _stream(stream))
         _check(code, "isam_fista")
         return FistaResult(out, info.iters_run, info.status, info.rel_res, info.resid2, info.l1, info.L)
+
+
+class _BorrowedPlan(Plan):
+    """A scan's plan inside a batch (owned by the batch)."""
+
+    def __init__(self, handle, geometry, batch):
+        self._lib = load_library()
+        self._h = handle
+        self.geometry = geometry
+        self.nx, self.nk = int(geometry.nx), int(geometry.nk)
+        self._batch = batch            # keeps the batch alive
+
+    def close(self) -> None:
+        self._h = ctypes.c_void_p()
+
+
+class Batch:
+    """Many B-scans of uneven size run together (one launch per pass per group of scans).
+
+    Packed device buffers hold scan i at elements [offsets[i], offsets[i+1]), each scan
+    row-major [nx_i][nk_i]: complex64 objects, float32 spectra.
+    """
+
+    def __init__(self, geometries, stream=None):
+        lib = load_library()
+        gs = [g if isinstance(g, Geometry) else Geometry.of(g) for g in geometries]
+        arr = (Geometry * len(gs))(*gs)
+        self.geometries = gs
+        self.n = len(gs)
+        self._h = ctypes.c_void_p()
+        _check(lib.isam_batch_plan(arr, self.n, _stream(stream), ctypes.byref(self._h)), "isam_batch_plan")
+        self._lib = lib
+        off = (ctypes.c_int64 * (self.n + 1))()
+        _check(lib.isam_batch_offsets(self._h, off), "isam_batch_offsets")
+        self.offsets = [int(v) for v in off]
+        self.total = self.offsets[-1]
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.isam_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def scan(self, t: torch.Tensor, i: int) -> torch.Tensor:
+        """View of scan i in a packed buffer, shaped [nx_i][nk_i]."""
+        g = self.geometries[i]
+        return t[self.offsets[i]:self.offsets[i + 1]].view(int(g.nx), int(g.nk))
+
+    def plan(self, i: int) -> Plan:
+        h = ctypes.c_void_p()
+        _check(self._lib.isam_batch_scan_plan(self._h, i, ctypes.byref(h)), "isam_batch_scan_plan")
+        return _BorrowedPlan(h, self.geometries[i], self)
+
+    def set_calibration(self, i: int, a2: float, a3: float, z_focus: float, stream=None) -> None:
+        _check(self._lib.isam_batch_set_calibration(self._h, i, a2, a3, z_focus, _stream(stream)),
+               "isam_batch_set_calibration")
+
+    def forward(self, eta: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        _dev_tensor(eta, torch.complex64, (self.total,), "eta")
+        if out is None:
+            out = torch.empty(self.total, dtype=torch.float32, device=eta.device)
+        _dev_tensor(out, torch.float32, (self.total,), "out")
+        _check(self._lib.isam_batch_forward(self._h, eta.data_ptr(), out.data_ptr(), _stream(stream)),
+               "isam_batch_forward")
+        return out
+
+    def adjoint(self, r: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        _dev_tensor(r, torch.float32, (self.total,), "r")
+        if out is None:
+            out = torch.empty(self.total, dtype=torch.complex64, device=r.device)
+        _dev_tensor(out, torch.complex64, (self.total,), "out")
+        _check(self._lib.isam_batch_adjoint(self._h, r.data_ptr(), out.data_ptr(), _stream(stream)),
+               "isam_batch_adjoint")
+        return out
+
+    def fista(self, y: torch.Tensor, lam, iters: int, w: torch.Tensor | None = None, tol: float = 0.0,
+              L=None, add_residual: bool = False, graph: bool = True, out: torch.Tensor | None = None,
+              stream=None):
+        """Returns (eta_packed, [FistaInfo per scan])."""
+        _dev_tensor(y, torch.float32, (self.total,), "y")
+        wp = None if w is None else _dev_tensor(w, torch.float32, (self.total,), "w").data_ptr()
+        if out is None:
+            out = torch.empty(self.total, dtype=torch.complex64, device=y.device)
+        _dev_tensor(out, torch.complex64, (self.total,), "out")
+        lam_a = (ctypes.c_float * self.n)(*[float(v) for v in lam])
+        L_a = None if L is None else (ctypes.c_double * self.n)(*[float(v) for v in L])
+        info = (FistaInfo * self.n)()
+        code = self._lib.isam_batch_fista(self._h, y.data_ptr(), lam_a, wp, int(iters), float(tol), L_a,
+                                          int(bool(add_residual)), 0 if graph else ISAM_BATCH_NO_GRAPH,
+                                          out.data_ptr(), info, _stream(stream))
+        _check(code, "isam_batch_fista")
+        return out, list(info)
+
+    def tune(self, reps: int = 10, stream=None) -> dict:
+        _check(self._lib.isam_batch_tune(self._h, int(reps), _stream(stream)), "isam_batch_tune")
+        return self.tiles()
+
+    def tiles(self) -> dict:
+        """{nx: (lanes of complex passes, lanes of real passes)} per lateral group."""
+        ng = ctypes.c_int32()
+        cap = 64
+        nx, c, r = (ctypes.c_int32 * cap)(), (ctypes.c_int32 * cap)(), (ctypes.c_int32 * cap)()
+        _check(self._lib.isam_batch_tiles(self._h, nx, c, r, cap, ctypes.byref(ng)), "isam_batch_tiles")
+        return {int(nx[i]): (int(c[i]), int(r[i])) for i in range(min(ng.value, cap))}
+
+    def set_tiles(self, nx: int, lanes_complex: int, lanes_real: int) -> None:
+        _check(self._lib.isam_batch_set_tiles(self._h, int(nx), int(lanes_complex), int(lanes_real)),
+               "isam_batch_set_tiles")

@@ -94,6 +94,25 @@ def test_entry_points_reject_null_plan(lib):
     assert lib.isam_calibration_grad(None, buf, buf, ctypes.byref(L), None) == -1
     assert lib.isam_plan_dims(None, None, None, None) == -1
     lib.isam_destroy(None)
+    h = ctypes.c_void_p()
+    assert lib.isam_batch_plan(None, 1, None, ctypes.byref(h)) == -1
+    assert lib.isam_batch_plan(ctypes.byref(_geom()), 0, None, ctypes.byref(h)) == -1
+    assert lib.isam_batch_forward(None, buf, buf, None) == -1
+    assert lib.isam_batch_adjoint(None, buf, buf, None) == -1
+    assert lib.isam_batch_tune(None, 1, None) == -1
+    assert lib.isam_batch_set_tiles(None, 256, 4, 4) == -1
+    assert lib.isam_batch_offsets(None, None) == -1
+    lib.isam_batch_destroy(None)
+
+
+def test_batch_plan_without_device_reports_enodev(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    gs = (P.Geometry * 2)(_geom(), _geom(nx=384))
+    h = ctypes.c_void_p()
+    assert lib.isam_batch_plan(gs, 2, None, ctypes.byref(h)) == -5
+    assert not h.value
 
 
 def test_valid_geometry_without_device_reports_enodev(lib):

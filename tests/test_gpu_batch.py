@@ -1,0 +1,159 @@
+"""GPU: batches of B-scans of uneven size.
+
+A batch runs each pass as one launch per group of scans over the same kernels as the
+single-scan path, so its results are compared bit for bit with the scans' own plans
+(isam_batch_scan_plan: same tables and tile widths), and one scan is also checked against
+the FP64 oracle.  The captured FISTA graph is replayed several times, with eager work in
+between, and every replay is compared with the eager (non-graph) run.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import phantoms as ph
+from _util import rel, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+# (nx, nk, edge phase2 [pi], edge phase3 [pi], focus rows)
+SCANS = [(64, 128, 10, 2, 16), (192, 256, 20, 4, 40), (256, 128, 30, -3, 20.5), (384, 256, 12, 0, -30),
+         (64, 256, 8, 1, 0), (192, 128, 16, 2, 7), (384, 128, 25, 5, 33)]
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1905_06058_amd as pkg
+    pkg.load_library()
+    return pkg
+
+
+def optics_list(scans=SCANS):
+    return [ph.custom_optics(nx, nk, edge_phase2=a * math.pi, edge_phase3=c * math.pi, focus_rows=f)
+            for nx, nk, a, c, f in scans]
+
+
+def packed(batch, arrays, dtype):
+    import torch
+    out = torch.empty(batch.total, dtype=dtype, device="cuda")
+    for i, a in enumerate(arrays):
+        batch.scan(out, i).copy_(to_dev(a, dtype))
+    return out
+
+
+def batch_data(opts, seed):
+    rng = np.random.default_rng(seed)
+    etas = [ph.complex_gaussian(rng, (o.nx, o.nk)) for o in opts]
+    rs = [rng.standard_normal((o.nx, o.nk)) for o in opts]
+    return etas, rs
+
+
+def test_batch_operator_matches_scan_plans_and_oracle(P):
+    import torch
+    opts = optics_list()
+    etas, rs = batch_data(opts, 1)
+    with P.Batch([P.Geometry.of(o) for o in opts]) as b:
+        eta = packed(b, etas, torch.complex64)
+        r = packed(b, rs, torch.float32)
+        s = b.forward(eta)
+        a = b.adjoint(r)
+        for i in range(b.n):
+            p = b.plan(i)
+            assert bool((b.scan(s, i) == p.forward(b.scan(eta, i).contiguous())).all()), i
+            assert bool((b.scan(a, i) == p.adjoint(b.scan(r, i).contiguous())).all()), i
+        i = 5                                              # 192 x 128, radix-3 lateral passes
+        g = O.Geometry.of(opts[i])
+        assert rel(to_host(b.scan(s, i)), O.forward_nufft(g, etas[i])) < 1e-5
+        assert rel(to_host(b.scan(a, i)), O.adjoint_nufft(g, rs[i])) < 1e-5
+
+
+def _problem(P, b, opts, seed):
+    import torch
+    rng = np.random.default_rng(seed)
+    ys = []
+    for i, o in enumerate(opts):
+        eta = ph.layers(rng, o.nx, o.nk, 2) + ph.point_scatterers(rng, o.nx, o.nk, o.nx // 4)
+        s = to_host(b.plan(i).forward(to_dev(eta)))
+        ys.append(ph.add_noise(s, 25.0, seed + i))
+    y = packed(b, ys, torch.float32)
+    L = [b.plan(i).lipschitz(iters=30, seed=0) for i in range(b.n)]
+    lam = [0.05 * b.plan(i).lambda_max(b.scan(y, i).contiguous()) for i in range(b.n)]
+    return y, L, lam
+
+
+def test_batch_fista_graph_replays_match_eager_and_scan_plans(P):
+    opts = optics_list()
+    with P.Batch([P.Geometry.of(o) for o in opts]) as b:
+        y, L, lam = _problem(P, b, opts, 7)
+        eager, info_e = b.fista(y, lam, 30, L=L, graph=False)
+        eager = eager.clone()
+        for rep in range(3):
+            b.forward(eager.clone())                       # eager work between replays
+            got, info = b.fista(y, lam, 30, L=L)
+            assert bool((got == eager).all()), rep
+            assert [x.resid2 for x in info] == [x.resid2 for x in info_e]
+        for i in range(b.n):
+            ref = b.plan(i).fista(b.scan(y, i).contiguous(), lam[i], 30, L=L[i])
+            assert rel(to_host(b.scan(eager, i)), to_host(ref.eta)) < 1e-6, i
+            assert abs(info_e[i].resid2 - ref.resid2) <= 1e-6 * ref.resid2
+
+
+def test_batch_fista_stop_rule_per_scan(P):
+    opts = optics_list()
+    with P.Batch([P.Geometry.of(o) for o in opts]) as b:
+        y, L, lam = _problem(P, b, opts, 9)
+        got, info = b.fista(y, lam, 300, tol=3e-3, L=L)
+        for i in range(b.n):
+            ref = b.plan(i).fista(b.scan(y, i).contiguous(), lam[i], 300, tol=3e-3, L=L[i])
+            assert info[i].iters_run == ref.iters, i
+            assert info[i].status == 0
+            assert rel(to_host(b.scan(got, i)), to_host(ref.eta)) < 1e-6, i
+
+
+def test_batch_tuner_keeps_results_consistent(P):
+    import torch
+    opts = optics_list()
+    etas, _ = batch_data(opts, 3)
+    with P.Batch([P.Geometry.of(o) for o in opts]) as b:
+        tiles = b.tune(reps=3)
+        assert set(tiles) == {64, 192, 256, 384}
+        for nx, (c, cr) in tiles.items():
+            assert c in (2, 4, 8) and cr in (2, 4, 8)
+        eta = packed(b, etas, torch.complex64)
+        s = b.forward(eta)
+        for i in range(b.n):
+            assert bool((b.scan(s, i) == b.plan(i).forward(b.scan(eta, i).contiguous())).all()), i
+        b.set_tiles(384, 2, 2)
+        assert b.tiles()[384] == (2, 2)
+        s2 = b.forward(eta)
+        assert rel(to_host(b.scan(s2, 3)), to_host(b.scan(s, 3))) < 1e-6
+
+
+def test_uneven_batch_of_sixty_four_scans(P):
+    """64 scans, nx drawn from {256, 384, ..., 1024}, nk from {1024, 2048}, own optics each."""
+    import torch
+    rng = np.random.default_rng(64)
+    opts = []
+    for _ in range(64):
+        nx = int(rng.choice(np.arange(256, 1025, 128)))
+        nk = int(rng.choice([1024, 2048]))
+        opts.append(ph.custom_optics(nx, nk, edge_phase2=float(rng.uniform(10, 40)) * math.pi,
+                                     edge_phase3=float(rng.uniform(-8, 8)) * math.pi,
+                                     focus_rows=float(rng.uniform(-nk / 4, nk / 4))))
+    with P.Batch([P.Geometry.of(o) for o in opts]) as b:
+        gen = torch.Generator(device="cuda").manual_seed(0)
+        eta = torch.randn(b.total, dtype=torch.complex64, device="cuda", generator=gen)
+        s = b.forward(eta)
+        a = b.adjoint(s)
+        for i in range(0, 64, 9):
+            p = b.plan(i)
+            assert bool((b.scan(s, i) == p.forward(b.scan(eta, i).contiguous())).all()), i
+            assert bool((b.scan(a, i) == p.adjoint(b.scan(s, i).contiguous())).all()), i
+        # adjoint identity over the whole batch: <A x, A x> = <x, A^H A x>
+        lhs = float((s.double() ** 2).sum())
+        rhs = float((eta.conj() * a).real.double().sum())
+        assert abs(lhs - rhs) <= 1e-5 * lhs
