@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--cpu-sample-nx", type=int, default=64,
                     help="A-scans of the oracle's timing sample (same depth length and optics)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle timing budget")
+    ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch leg")
+    ap.add_argument("--batch-iters", type=int, default=50, help="FISTA iterations of the uneven-batch leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a plain 64 MiB device copy (calibrates memory-traffic counters)")
     return ap.parse_args()
@@ -127,6 +129,82 @@ def cpu_baseline(w, sample_nx: int, budget_s: float, iters_full: int) -> dict:
                    f"matrices) on {sample_nx} of the {o.nx} A-scans ({sample_nx}x{o.nk}, same optics), "
                    f"{dt:.1f} s at {rate_sample:.3f} iter/s, scaled by {sample_nx}/{o.nx} "
                    f"(per-iteration work is linear in the A-scan count up to the lateral FFT's log factor)"),
+    }
+
+
+def batch_leg(P, torch, iters: int) -> dict:
+    """64 B-scans of uneven size (nx from {256, 384, ..., 1024}, nk from {1024, 2048}, own
+    phantom and dispersion each): one batch (tuned tiles, captured iteration graph) against
+    the same scans run one after another through their own plans (one launch per pass per scan)."""
+    import numpy as np
+    import phantoms as ph
+    rng = np.random.default_rng(3)
+    opts = []
+    for _ in range(64):
+        nx = int(rng.choice(np.arange(256, 1025, 128)))
+        nk = int(rng.choice([1024, 2048]))
+        opts.append(ph.custom_optics(nx, nk, edge_phase2=float(rng.uniform(10, 40)) * math.pi,
+                                     edge_phase3=float(rng.uniform(-8, 8)) * math.pi,
+                                     focus_rows=float(rng.uniform(-nk / 4, nk / 4))))
+    b = P.Batch([P.Geometry.of(o) for o in opts])
+    tiles = b.tune(reps=5)
+    y = torch.empty(b.total, dtype=torch.float32, device="cuda")
+    for i, o in enumerate(opts):
+        eta = ph.layers(rng, o.nx, o.nk, 3) + ph.point_scatterers(rng, o.nx, o.nk, o.nx // 2)
+        s = b.plan(i).forward(torch.from_numpy(eta).to(torch.complex64).cuda())
+        b.scan(y, i).copy_(s + 0.05 * s.abs().max() * torch.randn_like(s))
+    plans = [b.plan(i) for i in range(b.n)]
+    L = [p.lipschitz(iters=20, seed=0) for p in plans]
+    lam = [0.05 * p.lambda_max(b.scan(y, i).contiguous()) for i, p in enumerate(plans)]
+    ys = [b.scan(y, i).contiguous() for i in range(b.n)]
+    outs = [torch.empty((p.nx, p.nk), dtype=torch.complex64, device="cuda") for p in plans]
+    out = torch.empty(b.total, dtype=torch.complex64, device="cuda")
+
+    def timed(fn, reps=1):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    t_batch = timed(lambda: b.fista(y, lam, iters, L=L, out=out), 3)
+    t_eager = timed(lambda: b.fista(y, lam, iters, L=L, out=out, graph=False), 3)
+    t_scan = timed(lambda: [p.fista(ys[i], lam[i], iters, L=L[i], out=outs[i]) for i, p in enumerate(plans)], 3)
+    x = torch.randn(b.total, dtype=torch.complex64, device="cuda")
+    sb = torch.empty(b.total, dtype=torch.float32, device="cuda")
+    xs = [b.scan(x, i).contiguous() for i in range(b.n)]
+    ss = [torch.empty((p.nx, p.nk), dtype=torch.float32, device="cuda") for p in plans]
+
+    def pairs_batch():
+        for _ in range(10):
+            b.forward(x, out=sb)
+            b.adjoint(sb, out=x)
+
+    def pairs_scan():
+        for _ in range(10):
+            for i, p in enumerate(plans):
+                p.forward(xs[i], out=ss[i])
+                p.adjoint(ss[i], out=xs[i])
+
+    tp_batch = timed(pairs_batch, 2) / 10
+    tp_scan = timed(pairs_scan, 2) / 10
+    pts = b.total
+    b.close()
+    return {
+        "workload": "64 uneven B-scans, nx from {256..1024 step 128}, nk from {1024, 2048}, own phantom, "
+                    "dispersion and focus each; synthetic",
+        "scans": 64, "points": pts, "fista_iters": iters,
+        "tiles": {str(k): v for k, v in tiles.items()},
+        "batched_fista_iter_per_s": round(iters / t_batch, 2),
+        "batched_eager_fista_iter_per_s": round(iters / t_eager, 2),
+        "per_scan_fista_iter_per_s": round(iters / t_scan, 2),
+        "fista_speedup": round(t_scan / t_batch, 3),
+        "batched_pairs_per_s": round(1.0 / tp_batch, 2),
+        "per_scan_pairs_per_s": round(1.0 / tp_scan, 2),
+        "pairs_speedup": round(tp_scan / tp_batch, 3),
+        "note": "an iteration or pair covers all 64 scans; whole calls are timed (set-up and output included)",
     }
 
 
@@ -244,6 +322,8 @@ def main() -> int:
                     "algorithmic_bytes_per_launch": nbytes[dom], "avg_launch_us": round(dom_avg_s * 1e6, 3)}
     iter_bytes = sum(nbytes[k] for k in ("nufft_fwd", "nufft_adj", "fista_update"))
 
+    batched = None if args.no_batch else batch_leg(P, torch, args.batch_iters)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, args.cpu_sample_nx, args.cpu_seconds, args.steps)
@@ -273,6 +353,7 @@ def main() -> int:
                           "GBps": round(iter_bytes * args.steps / wall / 1e9, 1),
                           "frac": round(iter_bytes * args.steps / wall / 1e9 / HBM_PEAK_GBS, 4)},
         "passes": per_pass,
+        "batched": batched,
         "cpu_baseline": cpu,
         "gpu": torch.cuda.get_device_name(0),
     }
