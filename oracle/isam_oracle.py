@@ -46,7 +46,7 @@ __all__ = [
     "minmax_error", "forward", "adjoint", "forward_exact", "adjoint_exact",
     "forward_nufft", "adjoint_nufft", "soft_threshold", "lipschitz", "lambda_max",
     "fista", "dense_matrix", "Operator", "resampled_spectrum", "calibration_derivatives",
-    "calibration_gradient",
+    "calibration_gradient", "volume_q2", "VolumeOperator",
 ]
 
 
@@ -67,6 +67,8 @@ class Geometry:
     J: int = 6
     osf: int = 2
     kb_beta: float = 0.0
+    ny: int = 1              # lateral rows of a volume (1: a B-scan)
+    dy: float = 0.0          # their pitch (0: same as dx)
 
     @classmethod
     def of(cls, obj, **overrides) -> "Geometry":
@@ -413,6 +415,93 @@ def dense_matrix(g: Geometry, mode: str = "E") -> np.ndarray:
         e[i] = 1j
         M[:, 2 * i + 1] = op.A(e.reshape(g.nx, g.nk)).ravel()
     return M
+
+
+# --------------------------------------------------------------------------- volumes
+
+def volume_q2(g: Geometry) -> np.ndarray:
+    """q^2 = qx^2 + qy^2 of every lateral-frequency column of a volume, shape (ny, nx).
+
+    The 3-D form of the model (Sec. "Background": N = Nx Ny Nz): the lateral DFT runs
+    over both lateral axes (FFT order on each), and the Stolt map of Eq. 3 uses the
+    total lateral frequency.
+    """
+    dy = g.dy if g.dy > 0 else g.dx
+    qx = 2 * math.pi * np.fft.fftfreq(g.nx, d=1.0 / g.nx) / (g.nx * g.dx)
+    qy = 2 * math.pi * np.fft.fftfreq(g.ny, d=1.0 / g.ny) / (g.ny * dy)
+    return qy[:, None] ** 2 + qx[None, :] ** 2
+
+
+def _column_model(g: Geometry, q2: np.ndarray):
+    """Per-column pieces for arbitrary lateral frequencies (q2: one value per column).
+
+    Returns kz (propagating part, else 0), the modulation c of Eq. 13/16 (beam filter,
+    dispersion, focal reference) and the Stolt points (t, g0, tau) on the K-point grid;
+    arrays of shape (len(q2), nk).  These are the B-scan definitions of beam_filter,
+    modulation and stolt_points with q_l^2 replaced by the column's q^2.
+    """
+    G = grids(g)
+    q2 = np.asarray(q2, np.float64)
+    arg = 4 * G.k[None, :] ** 2 - q2[:, None]
+    prop = arg > 0
+    kz = np.sqrt(np.where(prop, arg, 0.0))
+    B = np.where(prop, np.exp(-q2[:, None] * g.waist ** 2 / 8.0), 0.0)
+    c = B * np.exp(1j * dispersion_phase(g)[None, :]) * np.exp(1j * (2 * G.k[None, :] - kz) * g.z_focus)
+    c = np.where(prop, c, 0.0)
+    t = np.mod(kz * G.dz, 2 * math.pi) * G.K / (2 * math.pi)
+    fl = np.floor(t)
+    return kz, c, (t, fl.astype(np.int64) - g.J // 2, t - fl)
+
+
+class VolumeOperator:
+    """A = Re o K^ and A^H for a volume eta[ny][nx][nz] (complex) -> s[ny][nx][nk] (real).
+
+    Eq. 16 with a two-dimensional unitary lateral DFT; each (qy, qx) column gets the
+    B-scan's resampling (mode E: direct nonuniform DFT; mode N: min-max NUFFT) and
+    modulation with q^2 = qx^2 + qy^2.
+    """
+
+    def __init__(self, g: Geometry, mode: str = "N"):
+        if mode not in ("E", "N"):
+            raise ValueError(mode)
+        self.g, self.mode = g, mode
+        self.q2 = volume_q2(g).ravel()                     # column index ly * nx + lx
+        self.kz, self.c, tables = _column_model(g, self.q2)
+        self.P = None
+        if mode == "N":
+            self.P = [_interp_matrix(g, i, None, tables) for i in range(self.q2.size)]
+
+    def _resample(self, eta_hat_cols):
+        G = grids(self.g)
+        X = np.empty_like(eta_hat_cols)
+        for i in range(eta_hat_cols.shape[0]):
+            if self.mode == "E":
+                X[i] = np.exp(1j * self.kz[i][:, None] * G.z[None, :]) @ eta_hat_cols[i]
+            else:
+                X[i] = self.P[i] @ _oversampled_spectrum(self.g, eta_hat_cols[i])[0]
+        return X / math.sqrt(self.g.nk)
+
+    def A(self, eta):
+        g = self.g
+        eta_hat = np.fft.fft2(np.asarray(eta, np.complex128), axes=(0, 1), norm="ortho")
+        X = self._resample(eta_hat.reshape(g.ny * g.nx, g.nk))
+        return np.real(np.fft.ifft2((self.c * X).reshape(g.ny, g.nx, g.nk), axes=(0, 1), norm="ortho"))
+
+    def AH(self, r):
+        g = self.g
+        G = grids(g)
+        R = np.fft.fft2(np.asarray(r, np.float64).astype(np.complex128), axes=(0, 1), norm="ortho")
+        Xp = np.conj(self.c) * R.reshape(g.ny * g.nx, g.nk)
+        s = kb_scaling(g)
+        out = np.empty_like(Xp)
+        for i in range(Xp.shape[0]):
+            if self.mode == "E":
+                out[i] = np.conj(np.exp(1j * self.kz[i][:, None] * G.z[None, :])).T @ Xp[i]
+            else:
+                full = np.fft.fft(self.P[i].conj().T @ Xp[i])
+                out[i] = s * full[np.mod(G.m, G.K)]
+        out /= math.sqrt(g.nk)
+        return np.fft.ifft2(out.reshape(g.ny, g.nx, g.nk), axes=(0, 1), norm="ortho")
 
 
 # --------------------------------------------------------------------------- calibration

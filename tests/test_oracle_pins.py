@@ -281,6 +281,59 @@ def test_focus_does_not_act_on_a_single_ascan():
     assert grad[2] == 0.0 and grad[0] != 0.0
 
 
+# --------------------------------------------------------------- volumes
+
+def _vol(nx, ny, nk, dy=None, **kw):
+    o = ph.custom_optics(nx, nk, edge_phase2=6 * math.pi, edge_phase3=2 * math.pi, focus_rows=5, **kw)
+    return O.Geometry.of(o, ny=ny, dy=dy if dy is not None else o.dx), o
+
+
+@pytest.mark.parametrize("mode", ["E", "N"])
+def test_volume_constant_along_y_is_the_bscan_operator(mode):
+    """Only qy = 0 columns: every y row of A eta equals the B-scan operator of that row."""
+    g, o = _vol(8, 4, 32, dy=5e-6)
+    rng = np.random.default_rng(11)
+    x0 = rand_obj(rng, 8, 32, clear_edge=False)
+    sv = O.VolumeOperator(g, mode).A(np.broadcast_to(x0, (4, 8, 32)))
+    s1 = O.forward(O.Geometry.of(o), x0, mode)
+    assert np.abs(sv - s1[None]).max() < 1e-12 * np.abs(s1).max()
+
+
+@pytest.mark.parametrize("mode", ["E", "N"])
+def test_volume_constant_along_x_is_the_bscan_operator_along_y(mode):
+    """Only qx = 0 columns: the volume acts along y as a B-scan of ny A-scans at pitch dy."""
+    g, o = _vol(4, 8, 32, dy=3e-6)
+    rng = np.random.default_rng(12)
+    x0 = rand_obj(rng, 8, 32, clear_edge=False)              # [y][z]
+    sv = O.VolumeOperator(g, mode).A(np.broadcast_to(x0[:, None, :], (8, 4, 32)))
+    gy = O.Geometry.of(o, nx=8, dx=3e-6)
+    s1 = O.forward(gy, x0, mode)
+    assert np.abs(sv - s1[:, None, :]).max() < 1e-12 * np.abs(s1).max()
+
+
+@pytest.mark.parametrize("mode", ["E", "N"])
+def test_volume_adjoint_and_transpose_symmetry(mode):
+    g, _ = _vol(8, 8, 32)
+    V = O.VolumeOperator(g, mode)
+    rng = np.random.default_rng(13)
+    x = ph.complex_gaussian(rng, (8, 8, 32))
+    y = rng.standard_normal((8, 8, 32))
+    Ax = V.A(x)
+    assert abs(np.sum(Ax * y) - np.real(np.vdot(x, V.AH(y)))) < 1e-12 * np.linalg.norm(Ax) * np.linalg.norm(y)
+    # square lateral grid, equal pitches: swapping x and y commutes with A
+    sw = V.A(np.swapaxes(x, 0, 1))
+    assert np.abs(sw - np.swapaxes(Ax, 0, 1)).max() < 1e-12 * np.abs(Ax).max()
+
+
+def test_volume_nufft_close_to_exact():
+    g, _ = _vol(8, 4, 64, dy=5e-6)
+    rng = np.random.default_rng(14)
+    x = ph.complex_gaussian(rng, (4, 8, 64))
+    e = O.VolumeOperator(g, "E").A(x)
+    n = O.VolumeOperator(g, "N").A(x)
+    assert 0 < rel(n, e) < 1e-5
+
+
 def test_soft_threshold_closed_form_and_edges():
     """Eq. 14 equals u - theta u/|u| for |u| > theta and 0 otherwise; theta = 0 is the identity."""
     rng = np.random.default_rng(7)
