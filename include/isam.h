@@ -23,10 +23,15 @@
  * centred on k0; the full-range depth grid has nz = nk rows of pitch
  * pi / band, row m in [-nz/2, nz/2) stored at depth index i = m + nz/2.
  *
+ * Volumes (ny > 1, the 3-D form N = nx ny nz of Sec. "Background"): the lateral
+ * DFT runs over both lateral axes, q^2 = qx^2 + qy^2, and every (qx, qy) column
+ * gets the same Stolt NUFFT.
+ *
  * Layouts (all row-major, caller-owned device memory):
- *   object eta    complex64 interleaved (re, im) float pairs, [nx][nk], depth contiguous
- *   spectra s, y  float32 [nx][nk], k contiguous
- *   weights w     float32 [nx][nk] (same layout as eta), or NULL for w = 1
+ *   object eta    complex64 interleaved (re, im) float pairs, [ny][nx][nk], depth contiguous
+ *   spectra s, y  float32 [ny][nx][nk], k contiguous
+ *   weights w     float32 [ny][nx][nk] (same layout as eta), or NULL for w = 1
+ * (ny = 1 for a B-scan: [nx][nk].)
  *
  * Every entry point returns ISAM_OK (0) or a negative ISAM_E* code; none aborts
  * or throws.  Work is enqueued on the given HIP stream (a hipStream_t passed as
@@ -48,8 +53,10 @@ enum {
     ISAM_OK = 0,
     ISAM_EINVAL = -1,        /* bad argument: null pointer, size or non-finite optics */
     ISAM_EALIAS = -2,        /* an output aliases an input */
-    ISAM_EUNSUPPORTED = -3,  /* valid but not built: J != 6, osf != 2, non power-of-two sizes,
-                                nx > 2048, nk > 4096, ny != 1, a Stolt-mapped column spanning
+    ISAM_EUNSUPPORTED = -3,  /* valid but not built: J != 6, osf != 2; nk not a power of two or
+                                above 4096; nx or ny not a built lateral length (powers of two up
+                                to 2048; 192, 320, 384, 448, 640, 768, 896, 1280, 1536, 1792);
+                                more than 2^30 object samples; a Stolt-mapped column spanning
                                 more than 5/4 of the oversampled depth period */
     ISAM_ENOMEM = -4,        /* device allocation failed */
     ISAM_ENODEV = -5,        /* no HIP device visible */
@@ -59,11 +66,12 @@ enum {
 
 typedef struct isam_plan_s* isam_plan_t;
 
-/* Geometry of one B-scan (SI units).  Sec. "Background" fixes N = nx ny nz with
- * nz the spectrometer length; Eq. 3 the Stolt map; Eq. 7 the dispersion. */
+/* Geometry of one B-scan or volume (SI units).  Sec. "Background" fixes
+ * N = nx ny nz with nz the spectrometer length; Eq. 3 the Stolt map; Eq. 7 the
+ * dispersion. */
 typedef struct {
-    int32_t nx, ny, nk;      /* A-scans, lateral rows (must be 1), spectral samples (= depth rows) */
-    double dx, dy;           /* lateral pitch [m] (dy unused while ny = 1) */
+    int32_t nx, ny, nk;      /* A-scans per row, rows (1 for a B-scan), spectral samples (= depth rows) */
+    double dx, dy;           /* lateral pitches [m] (dy unused when ny = 1) */
     double lambda_c;         /* centre wavelength [m] */
     double dlambda;          /* bandwidth [m]; sampling is uniform in k */
     double waist;            /* Gaussian beam waist w0 [m] of the beam filter B */
@@ -162,8 +170,9 @@ int isam_fista(isam_plan_t p, const float* y, float lambda, const float* w, int 
  *   2 lateral C2R                      subtracted in lateral frequency)
  *   3 lateral R2C                    4 Stolt NUFFT adjoint
  *   5 lateral FFT (inverse)          6 FISTA update pass
+ *   7 y transform of a volume (both directions; x passes count under 0, 2, 3, 5)
  * Synchronises the plan's last stream before reading. */
-#define ISAM_NPASS 7
+#define ISAM_NPASS 8
 int isam_timing(isam_plan_t p, int enable, double* ms_out, int64_t* count_out);
 
 /* ------------------------------------------------------------------------

@@ -225,7 +225,7 @@ int build_maps(isam_batch_t b) {
     }
     for (Group& g : b->nu) {
         add(g, 0, [](const isam_plan_s* p) { return isam::nufft_fwd_blocks(p); });
-        add(g, 1, [](const isam_plan_s* p) { return p->nx; });
+        add(g, 1, [](const isam_plan_s* p) { return p->ncol; });
     }
     if ((int)h.size() > b->maps_cap) {
         if (b->maps) (void)hipFree(b->maps);
@@ -268,7 +268,7 @@ void fill_static_records(isam_batch_t b) {
         for (int k = 0; k < NK_COUNT; ++k) {
             NuScan& r = b->nurec[k].host[i];
             r.a = p->nufft_args();
-            r.nblk = (k == NK_FWD_OP || k == NK_FWD_FISTA) ? rb : p->nx;
+            r.nblk = (k == NK_FWD_OP || k == NK_FWD_FISTA) ? rb : p->ncol;
         }
         NuScan* r = b->nurec[NK_FWD_OP].host.data() + i;
         r->in = p->etahat, r->in2 = nullptr, r->out = p->zh, r->partials = nullptr;
@@ -365,6 +365,8 @@ extern "C" int isam_batch_plan(const isam_geometry* geoms, int nscans, void* str
     if (!out) return ISAM_EINVAL;
     *out = nullptr;
     if (!geoms || nscans < 1) return ISAM_EINVAL;
+    for (int i = 0; i < nscans; ++i)
+        if (geoms[i].ny != 1) return ISAM_EUNSUPPORTED;        // batches hold B-scans
     isam_batch_s* b = new (std::nothrow) isam_batch_s();
     if (!b) return ISAM_ENOMEM;
     b->n = nscans;

@@ -19,15 +19,23 @@ bool lat_supported(int nx) {
 int lat_l(const isam_plan_s* p) {
     ISAM_LAT_SWITCH(return (LatCfg<N, C>::L));
 }
+// x transform of every A-scan row (for a volume: of each of the ny slabs [nx][nk]).
 hipError_t lat_c2c(const isam_plan_s* p, const float2* in, float2* out, int sign, hipStream_t s) {
-    ISAM_LAT_SWITCH(return (launch_c2c<N, C>(in, out, p->nk, p->twX[lat_l(p)], sign, s)));
+    const unsigned slab = (unsigned)(p->nx * p->nk);
+    ISAM_LAT_SWITCH(return (launch_c2c<N, C>(in, out, p->nk, p->twX[lat_l(p)], sign, s, p->ny, slab, slab)));
+}
+
+// y transform of a volume: length ny over ncols columns (row-major [ny][ncols] <-> blocked).
+hipError_t lat_c2c_y(const isam_plan_s* p, const float2* in, float2* out, int ncols, int sign, hipStream_t s) {
+    ISAM_LAT_DISPATCH(p->ny, p->lat_cy, ISAM_LAT_DEF_C,
+                      return (launch_c2c<N, C>(in, out, ncols, p->twY[LatCfg<N, C>::L], sign, s, 1, 0u, 0u)));
 }
 
 int lat_blocks(const isam_plan_s* p, int kind) {
     if (kind == 0) {
-        ISAM_LAT_SWITCH(return p->nk / C);
+        ISAM_LAT_SWITCH(return p->ny * (p->nk / C));
     }
-    ISAM_LAT_SWITCH_R(return p->nk / (2 * C));
+    ISAM_LAT_SWITCH_R(return p->ny * (p->nk / (2 * C)));
 }
 
 int lat_tile(int nx, int sel, int real) {

@@ -81,8 +81,11 @@ ISAM_DEV void lat_c2c_body(const float2* in, float2* out, int nk, const float2* 
 
 template <int N, int C, int SIGN, bool IB, bool OB>
 __global__ __launch_bounds__((LatCfg<N, C>::T)) void k_lat_c2c(const float2* in, float2* out, int nk,
-                                                          const float2* __restrict__ tw, float scale) {
-    lat_c2c_body<N, C, SIGN, IB, OB>(in, out, nk, tw, scale, blockIdx.x, gridDim.x);
+                                                          const float2* __restrict__ tw, float scale,
+                                                          unsigned slab_in, unsigned slab_out) {
+    // grid.y: independent slabs (the y rows of a volume) at the given element strides
+    lat_c2c_body<N, C, SIGN, IB, OB>(in + (size_t)blockIdx.y * slab_in, out + (size_t)blockIdx.y * slab_out, nk, tw,
+                                     scale, blockIdx.x, gridDim.x);
 }
 
 // Batched: workgroup b runs tile map[b].y of scan map[b].x (all scans of one lateral length N).
@@ -165,8 +168,10 @@ ISAM_DEV void lat_c2r_body(const float2* __restrict__ zh, float* __restrict__ s,
 template <int N, int C>
 __global__ __launch_bounds__((LatCfg<N, C>::T)) void k_lat_c2r(const float2* __restrict__ zh,
                                                           float* __restrict__ s, int nk,
-                                                          const float2* __restrict__ tw, float scale) {
-    lat_c2r_body<N, C>(zh, s, nk, tw, scale, blockIdx.x, gridDim.x);
+                                                          const float2* __restrict__ tw, float scale,
+                                                          unsigned slab_in, unsigned slab_out) {
+    lat_c2r_body<N, C>(zh + (size_t)blockIdx.y * slab_in, s + (size_t)blockIdx.y * slab_out, nk, tw, scale, blockIdx.x,
+                       gridDim.x);
 }
 
 template <int N, int C>
@@ -204,8 +209,10 @@ ISAM_DEV void lat_r2c_body(const float* __restrict__ r, float2* __restrict__ rh,
 template <int N, int C>
 __global__ __launch_bounds__((LatCfg<N, C>::T)) void k_lat_r2c(const float* __restrict__ r,
                                                           float2* __restrict__ rh, int nk,
-                                                          const float2* __restrict__ tw, float scale) {
-    lat_r2c_body<N, C>(r, rh, nk, tw, scale, blockIdx.x, gridDim.x);
+                                                          const float2* __restrict__ tw, float scale,
+                                                          unsigned slab_in, unsigned slab_out) {
+    lat_r2c_body<N, C>(r + (size_t)blockIdx.y * slab_in, rh + (size_t)blockIdx.y * slab_out, nk, tw, scale, blockIdx.x,
+                       gridDim.x);
 }
 
 template <int N, int C>
@@ -315,8 +322,11 @@ __global__ __launch_bounds__((LatCfg<N, C>::T)) void k_lat_fista(float2* __restr
                                                             float2* __restrict__ z,
                                                             const float* __restrict__ w, int nk,
                                                             const float2* __restrict__ tw, float scale,
-                                                            FistaStep fs, float* __restrict__ partials) {
-    lat_fista_body<N, C, NORMS>(eta_hat, ghat, z, w, nk, tw, scale, fs, partials, blockIdx.x, gridDim.x);
+                                                            FistaStep fs, float* __restrict__ partials,
+                                                            unsigned slab) {
+    const size_t o = (size_t)blockIdx.y * slab;
+    lat_fista_body<N, C, NORMS>(eta_hat + o, ghat + o, z + o, w ? w + o : nullptr, nk, tw, scale, fs,
+                                partials + (size_t)blockIdx.y * gridDim.x * kRedSlots, blockIdx.x, gridDim.x);
 }
 
 // Batched: the momentum weight of the iteration comes from the device (beta), the rest of
@@ -341,52 +351,57 @@ void set_lds(K kern, size_t bytes) {
 
 // sign -1: row-major object -> blocked lateral spectrum; sign +1: blocked -> row-major.
 template <int N, int C>
-hipError_t launch_c2c(const float2* in, float2* out, int nk, const float2* tw, int sign, hipStream_t s) {
+hipError_t launch_c2c(const float2* in, float2* out, int nk, const float2* tw, int sign, hipStream_t s, int slabs,
+                      unsigned slab_in, unsigned slab_out) {
     using Cf = LatCfg<N, C>;
     const float scale = 1.0f / sqrtf((float)N);
-    const dim3 grid(nk / C);
+    const dim3 grid(nk / C, slabs);
     if (sign < 0) {
         set_lds(k_lat_c2c<N, C, -1, false, true>, Cf::LDS);
-        ISAM_LAUNCH((k_lat_c2c<N, C, -1, false, true>), grid, dim3(Cf::T), Cf::LDS, s, in, out, nk, tw, scale);
+        ISAM_LAUNCH((k_lat_c2c<N, C, -1, false, true>), grid, dim3(Cf::T), Cf::LDS, s, in, out, nk, tw, scale,
+                    slab_in, slab_out);
     } else {
         set_lds(k_lat_c2c<N, C, +1, true, false>, Cf::LDS);
-        ISAM_LAUNCH((k_lat_c2c<N, C, +1, true, false>), grid, dim3(Cf::T), Cf::LDS, s, in, out, nk, tw, scale);
+        ISAM_LAUNCH((k_lat_c2c<N, C, +1, true, false>), grid, dim3(Cf::T), Cf::LDS, s, in, out, nk, tw, scale,
+                    slab_in, slab_out);
     }
     return hipGetLastError();
 }
 
 template <int N, int C>
-hipError_t launch_c2r(const float2* zh, float* sout, int nk, const float2* tw, hipStream_t s) {
+hipError_t launch_c2r(const float2* zh, float* sout, int nk, const float2* tw, hipStream_t s, int slabs,
+                      unsigned slab_in, unsigned slab_out) {
     using Cf = LatCfg<N, C>;
     set_lds(k_lat_c2r<N, C>, Cf::LDS);
-    ISAM_LAUNCH((k_lat_c2r<N, C>), dim3(nk / (2 * C)), dim3(Cf::T), Cf::LDS, s, zh, sout, nk, tw,
-                       1.0f / sqrtf((float)N));
+    ISAM_LAUNCH((k_lat_c2r<N, C>), dim3(nk / (2 * C), slabs), dim3(Cf::T), Cf::LDS, s, zh, sout, nk, tw,
+                       1.0f / sqrtf((float)N), slab_in, slab_out);
     return hipGetLastError();
 }
 
 template <int N, int C>
-hipError_t launch_r2c(const float* r, float2* rh, int nk, const float2* tw, hipStream_t s) {
+hipError_t launch_r2c(const float* r, float2* rh, int nk, const float2* tw, hipStream_t s, int slabs,
+                      unsigned slab_in, unsigned slab_out) {
     using Cf = LatCfg<N, C>;
     set_lds(k_lat_r2c<N, C>, Cf::LDS);
-    ISAM_LAUNCH((k_lat_r2c<N, C>), dim3(nk / (2 * C)), dim3(Cf::T), Cf::LDS, s, r, rh, nk, tw,
-                       1.0f / sqrtf((float)N));
+    ISAM_LAUNCH((k_lat_r2c<N, C>), dim3(nk / (2 * C), slabs), dim3(Cf::T), Cf::LDS, s, r, rh, nk, tw,
+                       1.0f / sqrtf((float)N), slab_in, slab_out);
     return hipGetLastError();
 }
 
 template <int N, int C>
 hipError_t launch_fista(float2* eh, const float2* gh, float2* z, const float* w, int nk, const float2* tw,
-                        FistaStep fs, float* partials, hipStream_t s) {
+                        FistaStep fs, float* partials, hipStream_t s, int slabs, unsigned slab) {
     using Cf = LatCfg<N, C>;
-    const dim3 grid(nk / C);
+    const dim3 grid(nk / C, slabs);
     const float scale = 1.0f / sqrtf((float)N);
     if (fs.norms) {
         set_lds(k_lat_fista<N, C, true>, Cf::LDS);
         ISAM_LAUNCH((k_lat_fista<N, C, true>), grid, dim3(Cf::T), Cf::LDS, s, eh, gh, z, w, nk, tw,
-                           scale, fs, partials);
+                           scale, fs, partials, slab);
     } else {
         set_lds(k_lat_fista<N, C, false>, Cf::LDS);
         ISAM_LAUNCH((k_lat_fista<N, C, false>), grid, dim3(Cf::T), Cf::LDS, s, eh, gh, z, w, nk, tw,
-                           scale, fs, partials);
+                           scale, fs, partials, slab);
     }
     return hipGetLastError();
 }

@@ -5,7 +5,8 @@ namespace isam {
 
 hipError_t lat_fista(const isam_plan_s* p, float2* eh, const float2* gh, float2* z, const float* w,
                      FistaStep fs, float* partials, hipStream_t s) {
-    ISAM_LAT_SWITCH(return (launch_fista<N, C>(eh, gh, z, w, p->nk, p->twX[lat_l(p)], fs, partials, s)));
+    ISAM_LAT_SWITCH(return (launch_fista<N, C>(eh, gh, z, w, p->nk, p->twX[lat_l(p)], fs, partials, s, p->ny,
+                                               (unsigned)(p->nx * p->nk))));
 }
 
 hipError_t lat_fista_batch(int nx, int sel, int norms, const LatScan* recs, const int2* map, int nblk,

@@ -121,7 +121,7 @@ ISAM_DEV void forward_column(const NufftArgs& a, const float2* __restrict__ etah
                 const int x = b + j * Cf::SPAN;
                 const int u = (x + a.mi + a.nk / 2) & (K - 1);      // depth index placed at x
                 const int uc = u < a.nk ? u : 0;
-                const float2 e = cscale(etahat[blk(col, uc, a.nx)], a.sm[uc]);
+                const float2 e = cscale(etahat[blk(col, uc, a.ncol)], a.sm[uc]);
                 v[i * Cf::RO + j] = u < a.nk ? e : c2(0.f, 0.f);
             }
         }
@@ -184,18 +184,17 @@ ISAM_DEV void nufft_fwd_body(const float2* __restrict__ etahat, const float2* __
     float2* wt = smem + 2 * Cf::BUF;
     for (int i = threadIdx.x; i < kWtabEntries; i += 2 * Cf::T) wt[i] = a.wtab[i];
     const int b = xcd_tile(bidx, nblk);                // neighbouring pairs on one XCD
-    const int colA = b;
-    const int colB = b == 0 ? (a.nx >= 2 ? a.nx / 2 : -1) : a.nx - b;
-    const int col = half == 0 ? colA : (colB >= 0 ? colB : colA);
+    const FwdPair pr = a.pairs[b];
+    const int col = half == 0 || pr.mode == 2 ? pr.a : pr.b;
     float2 xt[Cf::NPT];
     forward_column<K>(a, etahat, col, buf, wt, xt, tid);
-    const int nh = a.nx / 2 + 1;
+    const int nh = a.nhalf;
     float2 yh[Cf::NPT], yh1[Cf::NPT];
 #pragma unroll
     for (int r = 0; r < Cf::NPT; ++r) {
         const int n = min(tid + r * Cf::T, a.nk - 1);
-        yh[r] = yhat && half == 0 ? yhat[blk(b, n, nh)] : c2(0.f, 0.f);
-        yh1[r] = yhat && half == 0 && b == 0 && colB >= 0 ? yhat[blk(colB, n, nh)] : c2(0.f, 0.f);
+        yh[r] = yhat && half == 0 ? yhat[blk(pr.ha, n, nh)] : c2(0.f, 0.f);
+        yh1[r] = yhat && half == 0 && pr.hb >= 0 ? yhat[blk(pr.hb, n, nh)] : c2(0.f, 0.f);
     }
     __syncthreads();
     if (half == 1) {
@@ -214,19 +213,26 @@ ISAM_DEV void nufft_fwd_body(const float2* __restrict__ etahat, const float2* __
             const int n = tid + r * Cf::T;
             if (n >= a.nk) continue;
             const float2 xb = other[n];
-            if (b == 0) {
+            if (pr.mode != 0) {                        // self-paired column(s): Z = Re X
                 const float2 z0 = csub(c2(xt[r].x, 0.f), yh[r]);
-                zh[blk(0, n, nh)] = z0;
+                zh[blk(pr.ha, n, nh)] = z0;
                 acc[0] += cabs2(z0);
-                if (colB >= 0) {
+                if (pr.mode == 1) {
                     const float2 z1 = csub(c2(xb.x, 0.f), yh1[r]);
-                    zh[blk(colB, n, nh)] = z1;
+                    zh[blk(pr.hb, n, nh)] = z1;
                     acc[0] += cabs2(z1);
                 }
-            } else {
-                const float2 z = csub(cscale(cadd(xt[r], cconj(xb)), 0.5f), yh[r]);
-                zh[blk(b, n, nh)] = z;
-                acc[0] += 2.f * cabs2(z);
+            } else {                                   // partners: Z[a] = (X[a] + conj X[b]) / 2
+                const float2 zc = cscale(cadd(xt[r], cconj(xb)), 0.5f);
+                const float2 z = csub(zc, yh[r]);
+                zh[blk(pr.ha, n, nh)] = z;
+                if (pr.hb >= 0) {                      // both stored: Z[b] = conj Z[a]
+                    const float2 z1 = csub(cconj(zc), yh1[r]);
+                    zh[blk(pr.hb, n, nh)] = z1;
+                    acc[0] += cabs2(z) + cabs2(z1);
+                } else {
+                    acc[0] += 2.f * cabs2(z);
+                }
             }
         }
     }
@@ -272,14 +278,15 @@ __global__ __launch_bounds__(2 * NuCfg<K>::T) void k_nufft_calgrad(const float2*
     float2* wt = smem + 2 * Cf::BUF;
     for (int i = threadIdx.x; i < kWtabEntries; i += 2 * Cf::T) wt[i] = a.wtab[i];
     const int b = blockIdx.x;
-    const int colB = b == 0 ? (a.nx >= 2 ? a.nx / 2 : -1) : a.nx - b;
-    const bool active = half == 0 || colB >= 0;
-    const int col = half == 0 ? b : (colB >= 0 ? colB : b);
+    const FwdPair pr = a.pairs[b];
+    const bool active = half == 0 || pr.mode != 2;
+    const int col = half == 0 || pr.mode == 2 ? pr.a : pr.b;
     float2 xt[Cf::NPT];
     forward_column<K>(a, etahat, col, buf, wt, xt, tid);
-    const int nh = a.nx / 2 + 1;
-    const bool mirrored = col >= nh;
-    const int row = mirrored ? a.nx - col : col;
+    const int nh = a.nhalf;
+    // column b of a partner pair with no stored row has G[b] = conj G[a]
+    const bool mirrored = half == 1 && pr.hb < 0;
+    const int row = half == 0 || mirrored ? pr.ha : pr.hb;
     const double q2 = a.q2[col];
     float acc[3] = {0.f, 0.f, 0.f};
 #pragma unroll
@@ -329,9 +336,10 @@ ISAM_DEV void nufft_adj_body(const float2* __restrict__ rh, float2* __restrict__
     // half-spectrum row and the neighbouring rows (which share cache lines in the blocked
     // layout) are read through one XCD's L2.
     const int pos = xcd_tile(bidx, nblk);
-    const int col = pos == 0 ? 0 : (pos == a.nx - 1 ? a.nx / 2 : ((pos & 1) ? (pos + 1) / 2 : a.nx - pos / 2));
-    const int row = col <= a.nx / 2 ? col : a.nx - col;
-    const bool conj_in = col > a.nx / 2;
+    const int2 ce = a.adjcols[pos];
+    const int col = ce.x;
+    const bool conj_in = ce.y < 0;
+    const int row = conj_in ? -1 - ce.y : ce.y;
     for (int i = tid; i < kWtabEntries; i += T) wt[i] = a.wtab[i];
     for (int i = tid; i < K; i += T) Y[i] = c2(0.f, 0.f);
     const double q2 = a.q2[col];
@@ -341,7 +349,7 @@ ISAM_DEV void nufft_adj_body(const float2* __restrict__ rh, float2* __restrict__
 #pragma unroll
     for (int ch = 0; ch < Cf::NCH; ++ch) {
         const int n = min(ch * Cf::CS + tid, a.nk - 1);
-        xr[ch] = rh[blk(row, n, a.nx / 2 + 1)];
+        xr[ch] = rh[blk(row, n, a.nhalf)];
         en[ch] = a.En[n];
     }
     for (int ch = 0; ch < Cf::NCH; ++ch) {
@@ -411,7 +419,7 @@ ISAM_DEV void nufft_adj_body(const float2* __restrict__ rh, float2* __restrict__
             for (int j = 0; j < Cf::RO; ++j) {
                 const int x = b + j * Cf::SPAN;
                 const int u = (x + a.mi + a.nk / 2) & (K - 1);
-                if (u < a.nk) ghat[blk(col, u, a.nx)] = cscale(v[i * Cf::RO + j], a.sm[u]);
+                if (u < a.nk) ghat[blk(col, u, a.ncol)] = cscale(v[i * Cf::RO + j], a.sm[u]);
             }
         }
     }
@@ -445,7 +453,7 @@ hipError_t launch_fwd(const isam_plan_s* p, const float2* etahat, const float2* 
     set_lds(k_nufft_fwd<K>, Cf::LDS_FWD);
     NufftArgs a = p->nufft_args();
     a.stop = stop;
-    ISAM_LAUNCH(k_nufft_fwd<K>, dim3(std::max(1, p->nx / 2)), dim3(2 * Cf::T), Cf::LDS_FWD, s, etahat,
+    ISAM_LAUNCH(k_nufft_fwd<K>, dim3(nufft_fwd_blocks(p)), dim3(2 * Cf::T), Cf::LDS_FWD, s, etahat,
                        yhat, zh, a, partials);
     return hipGetLastError();
 }
@@ -455,7 +463,7 @@ hipError_t launch_calgrad(const isam_plan_s* p, const float2* etahat, const floa
                           hipStream_t s) {
     using Cf = NuCfg<K>;
     set_lds(k_nufft_calgrad<K>, Cf::LDS_FWD);
-    ISAM_LAUNCH(k_nufft_calgrad<K>, dim3(std::max(1, p->nx / 2)), dim3(2 * Cf::T), Cf::LDS_FWD, s, etahat, ghalf,
+    ISAM_LAUNCH(k_nufft_calgrad<K>, dim3(nufft_fwd_blocks(p)), dim3(2 * Cf::T), Cf::LDS_FWD, s, etahat, ghalf,
                 p->nufft_args(), partials);
     return hipGetLastError();
 }
@@ -466,7 +474,7 @@ hipError_t launch_adj(const isam_plan_s* p, const float2* rh, float2* ghat, hipS
     set_lds(k_nufft_adj<K>, Cf::LDS);
     NufftArgs a = p->nufft_args();
     a.stop = stop;
-    ISAM_LAUNCH(k_nufft_adj<K>, dim3(p->nx), dim3(Cf::T), Cf::LDS, s, rh, ghat, a);
+    ISAM_LAUNCH(k_nufft_adj<K>, dim3(p->ncol), dim3(Cf::T), Cf::LDS, s, rh, ghat, a);
     return hipGetLastError();
 }
 
@@ -537,16 +545,19 @@ hipError_t nufft_adj_batch(int K_, const NuScan* recs, const int2* map, int nblk
 // any propagating component), so no two samples share a slot of a cell; (2) the cells of a
 // chunk of samples, [g0_first + 1, g0_last + J], fit the chunk's slot array.  A margin of
 // a few cells covers FP64 rounding differences between host and device at floor boundaries.
-int nufft_fwd_blocks(const isam_plan_s* p) { return std::max(1, p->nx / 2); }
+int nufft_fwd_blocks(const isam_plan_s* p) { return p->npairs; }
 
 int nufft_span_ok(const isam_plan_s* p) {
     int cs = 64;
     int slotc = 0;
     ISAM_K_SWITCH_INT(p->K, cs = NuAdjCfg<K>::CS; slotc = NuAdjCfg<K>::SLOTC);
-    for (int i = 0; i < p->nx; ++i) {
-        const int l = (i < (p->nx + 1) / 2) ? i : i - p->nx;
-        const double q = 2.0 * 3.14159265358979323846 * l / (p->nx * p->g.dx);
-        const double q2 = q * q;
+    // q^2 depends on |lx| and |ly| only
+    const double kPiH = 3.14159265358979323846;
+    for (int i = 0; i < (p->nx / 2 + 1) * (p->ny / 2 + 1); ++i) {
+        const int l = i / (p->ny / 2 + 1), m = i % (p->ny / 2 + 1);
+        const double qx = 2.0 * kPiH * l / (p->nx * p->g.dx);
+        const double qy = p->ny > 1 ? 2.0 * kPiH * m / (p->ny * p->g.dy) : 0.0;
+        const double q2 = qx * qx + qy * qy;
         auto g0 = [&](int n, bool& prop) {
             const double k = p->kc + (double)(n - p->nk / 2) * p->dk;
             const double d = 4.0 * k * k - q2;

@@ -30,6 +30,13 @@ constexpr int kPieces = 32;       // piecewise-cubic pieces of the min-max weigh
 constexpr int kWtabEntries = kPieces * kJ * 4;   // float2 coefficients c0..c3 per piece and tap
 constexpr int kRedSlots = 8;      // scalars per workgroup in reduction partials
 
+// Columns of one forward-NUFFT workgroup.  mode 0: a and b are Hermitian partners
+// (a stored at half row ha; hb >= 0 if b is stored too); mode 1: a and b are two
+// self-paired columns (rows ha, hb); mode 2: a alone, self-paired.
+struct FwdPair {
+    int a, b, ha, hb, mode;
+};
+
 // Constant arguments of the per-column NUFFT kernels.
 struct NufftArgs {
     int nx, nk, K;
@@ -46,7 +53,12 @@ struct NufftArgs {
     const float2* tw;       // staged twiddles of the K-point FFT, radices up to 16
     const float2* tw8;      // staged twiddles of the K-point FFT, radices up to 8
     const int* stop;        // solver stop flag (non-zero: return at once), or null
+    int ncol;               // lateral-frequency columns (nx for a B-scan, nx * ny for a volume)
+    int nhalf;              // columns of the Hermitian half arrays (nx/2 + 1, times ny)
+    const FwdPair* pairs;   // forward NUFFT: column pair of each workgroup
+    const int2* adjcols;    // adjoint NUFFT: (column, half row; -1 - row if conjugated) per workgroup
 };
+
 
 // Device-side state of the relative-residual stop rule (Eq. 15): iteration at which it
 // held (0: not yet), status (ISAM_ENONFINITE on non-finite norms), last r_r.
@@ -104,11 +116,15 @@ struct isam_plan_s {
     isam_geometry g;
     int device;
     int nx, nk, K, nh;
+    int ny = 1;                   // A-scan rows of a volume (1 for a B-scan)
+    int ncol = 0, nhalf = 0;      // lateral-frequency columns: nx * ny, (nx/2 + 1) * ny
+    int npairs = 0;               // forward NUFFT workgroups
     double kc, band, dk, dz, cT, beta, mf;
     int mi;
     double mr;
     int lat_c = 0;                // lateral tile width of complex passes (lanes); 0 = default
     int lat_cr = 0;               // lateral tile width of real passes (lanes); 0 = default
+    int lat_cy = 0;               // tile width of the y transform of a volume (lanes); 0 = default
 
     // tables (device)
     double* q2 = nullptr;
@@ -119,6 +135,9 @@ struct isam_plan_s {
     float2* twK = nullptr;
     float2* twK8 = nullptr;
     float2* twX[5] = {};          // staged lateral twiddles for radix caps 2^2, 2^3, 2^4 (index = log2 cap)
+    float2* twY[5] = {};          // the same for the y transform of a volume
+    isam::FwdPair* pairs = nullptr;   // [npairs] forward NUFFT column pairs
+    int2* adjcols = nullptr;          // [ncol] adjoint NUFFT columns
     double* wscratch = nullptr;   // FP64 scratch of the weight-table build
 
     // workspace (device)
@@ -133,6 +152,8 @@ struct isam_plan_s {
     float* sbuf = nullptr;        // [nx][nk] real spectra scratch (FISTA: blocked data y)
     float* wbuf = nullptr;        // [nx][nk] blocked l1 weights of FISTA
     float2* zblk = nullptr;       // [nx][nk] blocked FISTA iterate z
+    float2* xs = nullptr;         // volume only: [ny] slabs of [nx][nk] x-spectra (blocked per slab)
+    float2* xsh = nullptr;        // volume only: [ny] slabs of [nh][nk] half x-spectra (blocked per slab)
     isam::Reduce red;
     double* host_sums = nullptr;  // pinned host copy of red.sums
     isam::StopState* stop = nullptr;       // device stop-rule state of the solver
@@ -155,6 +176,8 @@ namespace isam {
 
 // launchers (return hipError_t of the launch)
 hipError_t lat_c2c(const isam_plan_s* p, const float2* in, float2* out, int sign, hipStream_t s);
+// y transform of a volume (length ny) over ncols columns: sign -1 row-major -> blocked, +1 back.
+hipError_t lat_c2c_y(const isam_plan_s* p, const float2* in, float2* out, int ncols, int sign, hipStream_t s);
 hipError_t lat_c2r(const isam_plan_s* p, const float2* zh, float* s_out, hipStream_t st);
 hipError_t lat_r2c(const isam_plan_s* p, const float* r, float2* rh, hipStream_t st);
 // FISTA update pass; see solver.hip

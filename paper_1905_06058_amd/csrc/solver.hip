@@ -128,16 +128,21 @@ __global__ void k_axpy(float2* __restrict__ x, const float2* __restrict__ y, flo
         x[i] = csub(x[i], cscale(y[i], a));
 }
 
-// Row-major real [rows][cols] -> column-blocked, and column-blocked complex -> row-major.
-__global__ void k_to_blk_f(const float* __restrict__ src, float* __restrict__ dst, int rows, int cols) {
-    const size_t n = (size_t)rows * cols;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        dst[blk((int)(i / cols), (int)(i % cols), rows)] = src[i];
+// Row-major real [slabs][rows][cols] -> column-blocked per slab, and back for complex data.
+__global__ void k_to_blk_f(const float* __restrict__ src, float* __restrict__ dst, int rows, int cols, int slabs) {
+    const size_t m = (size_t)rows * cols, n = m * slabs;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t j = i % m;
+        dst[i - j + blk((int)(j / cols), (int)(j % cols), rows)] = src[i];
+    }
 }
-__global__ void k_from_blk_c(const float2* __restrict__ src, float2* __restrict__ dst, int rows, int cols) {
-    const size_t n = (size_t)rows * cols;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        dst[i] = src[blk((int)(i / cols), (int)(i % cols), rows)];
+__global__ void k_from_blk_c(const float2* __restrict__ src, float2* __restrict__ dst, int rows, int cols,
+                             int slabs) {
+    const size_t m = (size_t)rows * cols, n = m * slabs;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t j = i % m;
+        dst[i] = src[i - j + blk((int)(j / cols), (int)(j % cols), rows)];
+    }
 }
 
 __global__ void k_zero(float2* __restrict__ x, size_t n) {
@@ -244,17 +249,64 @@ namespace {
         if (e_ != hipSuccess) return ISAM_EHIP;        \
     } while (0)
 
+// Lateral transforms of the whole object: over x for a B-scan; over x then y for a volume
+// (x per slab into the slab-blocked x spectrum xs, then y, Eq. 2 in two dimensions).
+// Lateral spectra use the column index lx * ny + ly (see the column tables).
+int lat_fwd(isam_plan_t p, const float2* in, float2* out, hipStream_t s) {
+    if (p->ny == 1) {
+        TIMED(0, lat_c2c(p, in, out, -1, s));
+    } else {
+        TIMED(0, lat_c2c(p, in, p->xs, -1, s));
+        TIMED(7, lat_c2c_y(p, p->xs, out, p->nx * p->nk, -1, s));
+    }
+    return ISAM_OK;
+}
+int lat_inv(isam_plan_t p, const float2* in, float2* out, hipStream_t s) {
+    if (p->ny == 1) {
+        TIMED(5, lat_c2c(p, in, out, +1, s));
+    } else {
+        TIMED(7, lat_c2c_y(p, in, p->xs, p->nx * p->nk, +1, s));
+        TIMED(5, lat_c2c(p, p->xs, out, +1, s));
+    }
+    return ISAM_OK;
+}
+// Hermitian half spectrum -> real spectra (Eq. 5), and real spectra -> half spectrum.
+int lat_to_real(isam_plan_t p, const float2* zh, float* out, hipStream_t s) {
+    if (p->ny == 1) {
+        TIMED(2, lat_c2r(p, zh, out, s));
+    } else {
+        TIMED(7, lat_c2c_y(p, zh, p->xsh, p->nh * p->nk, +1, s));
+        TIMED(2, lat_c2r(p, p->xsh, out, s));
+    }
+    return ISAM_OK;
+}
+int lat_from_real(isam_plan_t p, const float* r, float2* rh, hipStream_t s) {
+    if (p->ny == 1) {
+        TIMED(3, lat_r2c(p, r, rh, s));
+    } else {
+        TIMED(3, lat_r2c(p, r, p->xsh, s));
+        TIMED(7, lat_c2c_y(p, p->xsh, rh, p->nh * p->nk, -1, s));
+    }
+    return ISAM_OK;
+}
+
+#define LAT_TRY(x)                  \
+    do {                            \
+        const int rc_ = (x);        \
+        if (rc_) return rc_;        \
+    } while (0)
+
 int forward_impl(isam_plan_t p, const float2* eta, float* s_out, hipStream_t s) {
-    TIMED(0, lat_c2c(p, eta, p->etahat, -1, s));
+    LAT_TRY(lat_fwd(p, eta, p->etahat, s));
     TIMED(1, nufft_fwd(p, p->etahat, nullptr, p->zh, nullptr, s));
-    TIMED(2, lat_c2r(p, p->zh, s_out, s));
+    LAT_TRY(lat_to_real(p, p->zh, s_out, s));
     return ISAM_OK;
 }
 
 int adjoint_impl(isam_plan_t p, const float* r, float2* eta_out, hipStream_t s) {
-    TIMED(3, lat_r2c(p, r, p->rh, s));
+    LAT_TRY(lat_from_real(p, r, p->rh, s));
     TIMED(4, nufft_adj(p, p->rh, p->ghat, s));
-    TIMED(5, lat_c2c(p, p->ghat, eta_out, +1, s));
+    LAT_TRY(lat_inv(p, p->ghat, eta_out, s));
     return ISAM_OK;
 }
 
@@ -263,10 +315,10 @@ int adjoint_impl(isam_plan_t p, const float* r, float2* eta_out, hipStream_t s) 
 // adjoint NUFFT passes meet in the lateral-frequency domain.  ||A eta - y||^2 partials go to
 // red.partials slot 0 (nufft_fwd_blocks workgroups).
 int normal_impl(isam_plan_t p, const float2* eta, const float2* yhat, float2* out, hipStream_t s) {
-    TIMED(0, lat_c2c(p, eta, p->etahat, -1, s));
+    LAT_TRY(lat_fwd(p, eta, p->etahat, s));
     TIMED(1, nufft_fwd(p, p->etahat, yhat, p->rh, p->red.partials, s));
     TIMED(4, nufft_adj(p, p->rh, p->ghat, s));
-    TIMED(5, lat_c2c(p, p->ghat, out, +1, s));
+    LAT_TRY(lat_inv(p, p->ghat, out, s));
     return ISAM_OK;
 }
 
@@ -274,21 +326,21 @@ int normal_impl(isam_plan_t p, const float2* eta, const float2* yhat, float2* ou
 
 extern "C" int isam_forward(isam_plan_t p, const void* eta, float* s_out, void* stream) {
     if (!p || !eta || !s_out) return ISAM_EINVAL;
-    const size_t n = (size_t)p->nx * p->nk;
+    const size_t n = (size_t)p->ncol * p->nk;
     if (overlaps(eta, n * 8, s_out, n * 4)) return ISAM_EALIAS;
     return forward_impl(p, (const float2*)eta, s_out, (hipStream_t)stream);
 }
 
 extern "C" int isam_adjoint(isam_plan_t p, const float* r, void* eta_out, void* stream) {
     if (!p || !r || !eta_out) return ISAM_EINVAL;
-    const size_t n = (size_t)p->nx * p->nk;
+    const size_t n = (size_t)p->ncol * p->nk;
     if (overlaps(r, n * 4, eta_out, n * 8)) return ISAM_EALIAS;
     return adjoint_impl(p, r, (float2*)eta_out, (hipStream_t)stream);
 }
 
 extern "C" int isam_normal(isam_plan_t p, const void* eta, void* eta_out, void* stream) {
     if (!p || !eta || !eta_out) return ISAM_EINVAL;
-    const size_t n = (size_t)p->nx * p->nk;
+    const size_t n = (size_t)p->ncol * p->nk;
     if (overlaps(eta, n * 8, eta_out, n * 8)) return ISAM_EALIAS;
     return normal_impl(p, (const float2*)eta, nullptr, (float2*)eta_out, (hipStream_t)stream);
 }
@@ -297,7 +349,7 @@ extern "C" int isam_lipschitz(isam_plan_t p, int iters, uint64_t seed, const voi
                               void* stream) {
     if (!p || !L_out || iters < 1) return ISAM_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    const size_t n = (size_t)p->nx * p->nk;
+    const size_t n = (size_t)p->ncol * p->nk;
     float2* x = p->vec;
     if (x0) {
         HIP_OK(hipMemcpyAsync(x, x0, n * sizeof(float2), hipMemcpyDeviceToDevice, s));
@@ -334,7 +386,7 @@ extern "C" int isam_lipschitz(isam_plan_t p, int iters, uint64_t seed, const voi
 extern "C" int isam_lambda_max(isam_plan_t p, const float* y, const float* w, double* out, void* stream) {
     if (!p || !y || !out) return ISAM_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    const size_t n = (size_t)p->nx * p->nk;
+    const size_t n = (size_t)p->ncol * p->nk;
     int rc = adjoint_impl(p, y, p->vec, s);
     if (rc) return rc;
     const int gb = grid_for(n);
@@ -350,8 +402,8 @@ extern "C" int isam_calibration_grad(isam_plan_t p, const void* eta, const float
                                      void* stream) {
     if (!p || !eta || !g || !grad_out) return ISAM_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    if (lat_c2c(p, (const float2*)eta, p->etahat, -1, s) != hipSuccess) return ISAM_EHIP;
-    if (lat_r2c(p, g, p->rh, s) != hipSuccess) return ISAM_EHIP;
+    if (int rc = lat_fwd(p, (const float2*)eta, p->etahat, s)) return rc;
+    if (int rc = lat_from_real(p, g, p->rh, s)) return rc;
     if (nufft_calgrad(p, p->etahat, p->rh, p->red.partials, s) != hipSuccess) return ISAM_EHIP;
     const int rc = sum_to_host(p, p->red.partials, nufft_fwd_blocks(p), 3, 0, s);
     if (rc) return rc;
@@ -367,23 +419,22 @@ namespace isam {
 // FISTA set-up (Alg. 1 with eta^1 = z^0 = 0): zero the state, bring the weights into the
 // blocked layout, and form the data's lateral spectrum yhat = F(y) (Hermitian half, blocked).
 int fista_prepare(isam_plan_t p, const float* y, const float* w, hipStream_t s) {
-    const size_t n = (size_t)p->nx * p->nk;
+    const size_t n = (size_t)p->ncol * p->nk;
     const int gb = grid_for(n);
     if (nufft_fwd_blocks(p) + lat_blocks(p, 0) > p->red.maxBlocks) return ISAM_EUNSUPPORTED;
     hipLaunchKernelGGL(k_zero, dim3(gb), dim3(256), 0, s, p->zblk, n);
     hipLaunchKernelGGL(k_zero, dim3(gb), dim3(256), 0, s, p->fista_hat, n);
-    if (w) hipLaunchKernelGGL(k_to_blk_f, dim3(gb), dim3(256), 0, s, w, p->wbuf, p->nx, p->nk);
+    if (w) hipLaunchKernelGGL(k_to_blk_f, dim3(gb), dim3(256), 0, s, w, p->wbuf, p->nx, p->nk, p->ny);
     HIP_OK(hipGetLastError());
-    TIMED(3, lat_r2c(p, y, p->yhat, s));
-    return ISAM_OK;
+    return lat_from_real(p, y, p->yhat, s);
 }
 
 // FISTA output: z^k in row-major order, plus the optional residual step of Alg. 1,
 // z += (1/L) A^H (y - A z).
 int fista_finish(isam_plan_t p, double L, int add_residual, float2* out, hipStream_t s) {
-    const size_t n = (size_t)p->nx * p->nk;
+    const size_t n = (size_t)p->ncol * p->nk;
     const int gb = grid_for(n);
-    hipLaunchKernelGGL(k_from_blk_c, dim3(gb), dim3(256), 0, s, p->zblk, out, p->nx, p->nk);
+    hipLaunchKernelGGL(k_from_blk_c, dim3(gb), dim3(256), 0, s, p->zblk, out, p->nx, p->nk, p->ny);
     HIP_OK(hipGetLastError());
     if (add_residual) {
         int rc = normal_impl(p, out, p->yhat, p->vec, s);
@@ -401,7 +452,7 @@ extern "C" int isam_fista(isam_plan_t p, const float* y, float lambda, const flo
                           void* stream) {
     if (!p || !y || !eta_out || max_iter < 0 || !(lambda >= 0.f) || !(tol >= 0.f) || !std::isfinite(L))
         return ISAM_EINVAL;
-    const size_t n = (size_t)p->nx * p->nk;
+    const size_t n = (size_t)p->ncol * p->nk;
     if (overlaps(y, n * 4, eta_out, n * 8)) return ISAM_EALIAS;
     if (w && overlaps(w, n * 4, eta_out, n * 8)) return ISAM_EALIAS;
     hipStream_t s = (hipStream_t)stream;
@@ -430,14 +481,26 @@ extern "C" int isam_fista(isam_plan_t p, const float* y, float lambda, const flo
     fs.stop = stop;
     hipLaunchKernelGGL(k_stop_reset, dim3(1), dim3(64), 0, s, p->stop);
     HIP_OK(hipGetLastError());
+    const bool vol = p->ny > 1;
     double t = 1.0, rel_res = -1.0;
     int iters_run = max_iter, status = ISAM_OK;
     for (int k = 1; k <= max_iter; ++k) {
-        TIMED(1, nufft_fwd(p, p->fista_hat, p->yhat, p->rh, part_r, s, stop));
+        // the momentum point lives in the x spectrum; a volume's NUFFT needs the y transform too
+        const float2* eh = p->fista_hat;
+        if (vol) {
+            TIMED(7, lat_c2c_y(p, p->fista_hat, p->etahat, p->nx * p->nk, -1, s));
+            eh = p->etahat;
+        }
+        TIMED(1, nufft_fwd(p, eh, p->yhat, p->rh, part_r, s, stop));
         TIMED(4, nufft_adj(p, p->rh, p->ghat, s, stop));
+        const float2* gx = p->ghat;
+        if (vol) {
+            TIMED(7, lat_c2c_y(p, p->ghat, p->xs, p->nx * p->nk, +1, s));
+            gx = p->xs;
+        }
         const double t_next = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
         fs.beta = (float)((t - 1.0) / t_next);
-        TIMED(6, lat_fista(p, p->fista_hat, p->ghat, z, wb, fs, part_f, s));
+        TIMED(6, lat_fista(p, p->fista_hat, gx, z, wb, fs, part_f, s));
         if (fs.norms) {
             hipLaunchKernelGGL(k_stop_check, dim3(1), dim3(256), 0, s, part_f, fb, p->stop, k, tol);
             HIP_OK(hipGetLastError());

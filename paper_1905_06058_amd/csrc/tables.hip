@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "common.hpp"
 #include "fft.hpp"
@@ -39,8 +40,8 @@ constexpr double kPi = 3.14159265358979323846;
 bool is_pow2(long n) { return n > 0 && (n & (n - 1)) == 0; }
 
 struct TableArgs {
-    int nx, nk, K;
-    double dx, waist, kc, dk, a2, a3, zf, beta;
+    int nx, ny, nk, K;
+    double dx, dy, waist, kc, dk, a2, a3, zf, beta;
     double* q2;
     float* Bl;
     float2* En;
@@ -56,11 +57,16 @@ __device__ double kb_scale(double m, int K, double beta) {
 
 __global__ void k_tables(TableArgs a) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < a.nx) {
-        const int l = (i < (a.nx + 1) / 2) ? i : i - a.nx;       // FFT order
-        const double q = 2.0 * kPi * l / (a.nx * a.dx);
-        a.q2[i] = q * q;
-        a.Bl[i] = (float)exp(-q * q * a.waist * a.waist / 8.0);
+    if (i < a.nx * a.ny) {
+        // column i = lx * ny + ly; lateral frequencies in FFT order
+        const int lx = i / a.ny, ly = i % a.ny;
+        const int l = (lx < (a.nx + 1) / 2) ? lx : lx - a.nx;
+        const int m = (ly < (a.ny + 1) / 2) ? ly : ly - a.ny;
+        const double qx = 2.0 * kPi * l / (a.nx * a.dx);
+        const double qy = a.ny > 1 ? 2.0 * kPi * m / (a.ny * a.dy) : 0.0;
+        const double q2 = qx * qx + qy * qy;
+        a.q2[i] = q2;
+        a.Bl[i] = (float)exp(-q2 * a.waist * a.waist / 8.0);
     }
     if (i < a.nk) {
         const double d = (i - a.nk / 2) * a.dk;                   // k_n - k0
@@ -251,6 +257,39 @@ void cubic_nodes(double nodes[4], double vinv[16]) {
         for (int i = 0; i < 4; ++i) vinv[q * 4 + i] = V[q][4 + i];
 }
 
+// Lateral-frequency columns (Eq. 2 over one or two lateral axes): column col = lx * ny + ly;
+// the Hermitian half keeps lx <= nx/2 at the same index.  The partner of (lx, ly) is
+// (-lx mod nx, -ly mod ny).  Forward NUFFT workgroups: first the self-paired columns, two
+// per workgroup, then one partner pair per workgroup; adjoint workgroups: each stored column
+// followed by its unstored partner (for a B-scan the order 0, 1, nx-1, 2, nx-2, ..., nx/2).
+void build_columns(const isam_plan_s* p, std::vector<isam::FwdPair>& pairs, std::vector<int2>& cols) {
+    const int nx = p->nx, ny = p->ny, nh = p->nhalf;
+    auto partner = [&](int c) { return ((nx - c / ny) % nx) * ny + (ny - c % ny) % ny; };
+    std::vector<int> self;
+    for (int c = 0; c < nh; ++c)
+        if (partner(c) == c) self.push_back(c);
+    for (size_t i = 0; i < self.size(); i += 2) {
+        if (i + 1 < self.size())
+            pairs.push_back({self[i], self[i + 1], self[i], self[i + 1], 1});
+        else
+            pairs.push_back({self[i], self[i], self[i], -1, 2});
+    }
+    for (int c = 0; c < nh; ++c) {
+        const int q = partner(c);
+        if (q == c) continue;
+        if (q < nh) {
+            if (c < q) pairs.push_back({c, q, c, q, 0});
+        } else {
+            pairs.push_back({c, q, c, -1, 0});
+        }
+    }
+    for (int c = 0; c < nh; ++c) {
+        cols.push_back(make_int2(c, c));
+        const int q = partner(c);
+        if (q >= nh) cols.push_back(make_int2(q, -1 - c));
+    }
+}
+
 int validate(const isam_geometry* g) {
     if (!g) return ISAM_EINVAL;
     if (g->nx < 1 || g->ny < 1 || g->nk < 2) return ISAM_EINVAL;
@@ -263,7 +302,9 @@ int validate(const isam_geometry* g) {
         if (!std::isfinite(v)) return ISAM_EINVAL;
     if (!(g->dx > 0) || !(g->lambda_c > 0) || !(g->dlambda > 0) || g->waist < 0) return ISAM_EINVAL;
     if (!(g->dlambda < g->lambda_c)) return ISAM_EINVAL;
-    if (g->ny != 1) return ISAM_EUNSUPPORTED;
+    if (g->ny > 1 && (!std::isfinite(g->dy) || !(g->dy > 0))) return ISAM_EINVAL;
+    if (g->ny > 1 && !lat_supported(g->ny)) return ISAM_EUNSUPPORTED;
+    if ((int64_t)g->nx * g->ny * g->nk > ((int64_t)1 << 30)) return ISAM_EUNSUPPORTED;   // 32-bit offsets
     if (g->J != kJ || g->osf != 2) return ISAM_EUNSUPPORTED;
     if (!lat_supported(g->nx)) return ISAM_EUNSUPPORTED;
     if (!is_pow2(g->nk) || g->nk > 4096) return ISAM_EUNSUPPORTED;
@@ -278,6 +319,9 @@ void derive(isam_plan_s* p, const isam_geometry* g) {
     p->nk = g->nk;
     p->K = g->osf * g->nk;
     p->nh = g->nx / 2 + 1;
+    p->ny = g->ny;
+    p->ncol = g->nx * g->ny;
+    p->nhalf = p->nh * g->ny;
     p->kc = 2.0 * kPi / g->lambda_c;
     p->band = 2.0 * kPi * g->dlambda / (g->lambda_c * g->lambda_c);
     p->dk = p->band / g->nk;
@@ -296,10 +340,13 @@ void derive(isam_plan_s* p, const isam_geometry* g) {
     } while (0)
 
 int build_twiddles(isam_plan_s* p, hipStream_t s) {
-    // staged tables: depth FFT (radix caps 16 and 8), lateral FFT (caps 4, 8, 16)
+    // staged tables: depth FFT (radix caps 16 and 8), lateral FFT (caps 4, 8, 16), and for a
+    // volume the y transform
     struct Item { int N, L; float2* dst; };
-    const Item items[] = {{p->K, 4, p->twK}, {p->K, 3, p->twK8}, {p->nx, 2, p->twX[2]}, {p->nx, 3, p->twX[3]},
-                          {p->nx, 4, p->twX[4]}};
+    std::vector<Item> items = {{p->K, 4, p->twK}, {p->K, 3, p->twK8}, {p->nx, 2, p->twX[2]}, {p->nx, 3, p->twX[3]},
+                               {p->nx, 4, p->twX[4]}};
+    if (p->ny > 1)       // the y transform of a volume
+        for (int L = 2; L <= 4; ++L) items.push_back({p->ny, L, p->twY[L]});
     int ntot = 0;
     for (const Item& it : items) ntot += fft_stage_len(it.N, it.L);
     int2* h = nullptr;
@@ -333,9 +380,11 @@ int build_twiddles(isam_plan_s* p, hipStream_t s) {
 int build_calibrated_tables(isam_plan_s* p, hipStream_t s) {
     TableArgs a;
     a.nx = p->nx;
+    a.ny = p->ny;
     a.nk = p->nk;
     a.K = p->K;
     a.dx = p->g.dx;
+    a.dy = p->g.dy;
     a.waist = p->g.waist;
     a.kc = p->kc;
     a.dk = p->dk;
@@ -347,7 +396,7 @@ int build_calibrated_tables(isam_plan_s* p, hipStream_t s) {
     a.Bl = p->Bl;
     a.En = p->En;
     a.sm = p->sm;
-    const int n = std::max(p->nx, p->nk);
+    const int n = std::max(p->ncol, p->nk);
     hipLaunchKernelGGL(k_tables, dim3((n + 255) / 256), dim3(256), 0, s, a);
     HIP_TRY(hipGetLastError());
 
@@ -381,9 +430,10 @@ int dalloc(T** ptr, size_t n) {
 }
 
 void release(isam_plan_s* p) {
-    void* ptrs[] = {p->q2, p->Bl, p->En, p->sm, p->wtab, p->twK, p->twK8, p->twX[2], p->twX[3], p->twX[4], p->wscratch,
+    void* ptrs[] = {p->q2, p->Bl, p->En, p->sm, p->wtab, p->twK, p->twK8, p->twX[2], p->twX[3], p->twX[4],
+                    p->twY[2], p->twY[3], p->twY[4], p->pairs, p->adjcols, p->wscratch,
                     p->etahat, p->zh, p->rh, p->ghat, p->fista_hat, p->yhat, p->vec, p->sbuf, p->wbuf, p->zblk,
-                    p->red.partials, p->red.sums};
+                    p->xs, p->xsh, p->red.partials, p->red.sums};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     if (p->host_sums) (void)hipHostFree(p->host_sums);
@@ -417,6 +467,10 @@ isam::NufftArgs isam_plan_s::nufft_args() const {
     a.tw = twK;
     a.tw8 = twK8;
     a.stop = nullptr;
+    a.ncol = ncol;
+    a.nhalf = nhalf;
+    a.pairs = pairs;
+    a.adjcols = adjcols;
     return a;
 }
 
@@ -440,12 +494,29 @@ extern "C" int isam_plan(const isam_geometry* g, void* stream, isam_plan_t* out)
     p->device = dev;
     if (const char* env = std::getenv("ISAM_LAT_C")) p->lat_c = std::atoi(env);
     if (const char* env = std::getenv("ISAM_LAT_CR")) p->lat_cr = std::atoi(env);
-    const size_t full = (size_t)p->nx * p->nk, half = (size_t)p->nh * p->nk;
-    p->red.maxBlocks = std::max(std::max(p->nx, 2 * p->nk), 2048) + 64;   // lateral passes use up to 2 nk blocks
+    const size_t full = (size_t)p->ncol * p->nk, half = (size_t)p->nhalf * p->nk;
+    // forward NUFFT (ncol / 2 workgroups) plus the update pass (up to 2 nk per slab)
+    p->red.maxBlocks = p->ncol + 2 * p->nk * p->ny + 2048;
     const int nsums = kPieces * 4 * kJ + (2 * kJ - 1);
+    std::vector<isam::FwdPair> hp;
+    std::vector<int2> hc;
+    build_columns(p, hp, hc);
+    p->npairs = (int)hp.size();
     rc = ISAM_OK;
-    rc = rc ? rc : dalloc(&p->q2, p->nx);
-    rc = rc ? rc : dalloc(&p->Bl, p->nx);
+    rc = rc ? rc : dalloc(&p->q2, p->ncol);
+    rc = rc ? rc : dalloc(&p->Bl, p->ncol);
+    rc = rc ? rc : dalloc(&p->pairs, hp.size());
+    rc = rc ? rc : dalloc(&p->adjcols, hc.size());
+    if (rc == ISAM_OK && (hipMemcpy(p->pairs, hp.data(), hp.size() * sizeof(isam::FwdPair), hipMemcpyHostToDevice) !=
+                              hipSuccess ||
+                          hipMemcpy(p->adjcols, hc.data(), hc.size() * sizeof(int2), hipMemcpyHostToDevice) !=
+                              hipSuccess))
+        rc = ISAM_EHIP;
+    if (p->ny > 1) {
+        for (int L = 2; L <= 4; ++L) rc = rc ? rc : dalloc(&p->twY[L], fft_stage_len(p->ny, L));
+        rc = rc ? rc : dalloc(&p->xs, full);
+        rc = rc ? rc : dalloc(&p->xsh, half);
+    }
     rc = rc ? rc : dalloc(&p->En, p->nk);
     rc = rc ? rc : dalloc(&p->sm, p->nk);
     rc = rc ? rc : dalloc(&p->wtab, kWtabEntries);

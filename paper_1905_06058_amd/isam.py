@@ -34,7 +34,7 @@ EXPORTS = (
 ISAM_BATCH_NO_GRAPH = 1
 
 PASS_NAMES = ("lateral_fft_fwd", "nufft_fwd", "lateral_c2r", "lateral_r2c", "nufft_adj",
-              "lateral_fft_inv", "fista_update")
+              "lateral_fft_inv", "fista_update", "lateral_y")
 
 
 class IsamError(RuntimeError):
@@ -56,7 +56,7 @@ class Geometry(ctypes.Structure):
     @classmethod
     def of(cls, o, **overrides) -> "Geometry":
         """From any record carrying nx, nk, dx, lambda_c, dlambda, waist, z_focus, a2, a3."""
-        vals = dict(nx=o.nx, ny=1, nk=o.nk, dx=o.dx, dy=getattr(o, "dy", o.dx),
+        vals = dict(nx=o.nx, ny=getattr(o, "ny", 1), nk=o.nk, dx=o.dx, dy=getattr(o, "dy", o.dx),
                     lambda_c=o.lambda_c, dlambda=o.dlambda, waist=o.waist, z_focus=o.z_focus,
                     a2=o.a2, a3=o.a3, J=getattr(o, "J", 6), osf=getattr(o, "osf", 2),
                     kb_beta=getattr(o, "kb_beta", 0.0))
@@ -165,14 +165,15 @@ class Plan:
         lib = load_library()
         g = geometry if isinstance(geometry, Geometry) else Geometry.of(geometry)
         self.geometry = g
-        self.nx, self.nk = int(g.nx), int(g.nk)
+        self.nx, self.ny, self.nk = int(g.nx), int(g.ny), int(g.nk)
         self._h = ctypes.c_void_p()
         _check(lib.isam_plan(ctypes.byref(g), _stream(stream), ctypes.byref(self._h)), "isam_plan")
         self._lib = lib
 
     @property
     def shape(self):
-        return (self.nx, self.nk)
+        """(nx, nk) for a B-scan, (ny, nx, nk) for a volume."""
+        return (self.nx, self.nk) if self.ny == 1 else (self.ny, self.nx, self.nk)
 
     def close(self) -> None:
         if getattr(self, "_h", None) and self._h.value:
@@ -279,7 +280,7 @@ class _BorrowedPlan(Plan):
         self._lib = load_library()
         self._h = handle
         self.geometry = geometry
-        self.nx, self.nk = int(geometry.nx), int(geometry.nk)
+        self.nx, self.ny, self.nk = int(geometry.nx), int(geometry.ny), int(geometry.nk)
         self._batch = batch            # keeps the batch alive
 
     def close(self) -> None:

@@ -64,7 +64,9 @@ def _plan_rc(lib, g):
     (dict(nx=384), -5),            # 3 x 128: valid, but no device here
     (dict(nk=8192), -3),
     (dict(nx=4096), -3),
-    (dict(ny=2), -3),
+    (dict(ny=2), -5),              # a volume: valid, but no device here
+    (dict(ny=3), -3),
+    (dict(ny=2, dy=0.0), -1),
     (dict(dx=0.0), -1),
     (dict(dlambda=-1e-9), -1),
     (dict(a2=float("nan")), -1),
