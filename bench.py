@@ -45,6 +45,8 @@ def parse():
                     help="A-scans of the oracle's timing sample (same depth length and optics)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle timing budget")
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch leg")
+    ap.add_argument("--no-volume", action="store_true", help="skip the 256x256x2048 volume leg")
+    ap.add_argument("--volume-iters", type=int, default=50, help="FISTA iterations of the volume leg")
     ap.add_argument("--batch-iters", type=int, default=50, help="FISTA iterations of the uneven-batch leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a plain 64 MiB device copy (calibrates memory-traffic counters)")
@@ -208,6 +210,61 @@ def batch_leg(P, torch, iters: int) -> dict:
     }
 
 
+def volume_leg(P, torch, iters: int) -> dict:
+    """256 x 256 A-scans x 2048 samples (a 1.07 GB complex64 object): 20000 scatterers plus
+    3 curved layers, FISTA for `iters` iterations; per-pass kernel times from isam_timing."""
+    import numpy as np
+    import phantoms as ph
+    ny = nx = 256
+    nk = 2048
+    o = ph.custom_optics(nx, nk, edge_phase2=40 * math.pi, edge_phase3=8 * math.pi, focus_rows=nk // 4)
+    plan = P.Plan(P.Geometry.of(o, ny=ny, dy=o.dx))
+    rng = np.random.default_rng(5)
+    eta = torch.zeros((ny, nx, nk), dtype=torch.complex64, device="cuda")
+    yy, xx = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    for j in range(3):                                     # curved layers: depth row = smooth surface
+        depth = (nk // 2 + (j - 1) * nk // 6 + 40 * np.sin(2 * np.pi * (xx / nx + j / 3))
+                 + 30 * np.cos(2 * np.pi * yy / ny)).astype(np.int64)
+        amp = 0.5 + 0.5 * rng.random((ny, nx))
+        flat = (yy * nx + xx) * nk + np.clip(depth, 0, nk - 1)
+        eta.view(-1)[torch.from_numpy(flat.ravel()).cuda()] += torch.from_numpy(amp.ravel()).to(torch.complex64).cuda()
+    pts = torch.from_numpy(rng.integers(0, ny * nx * nk, 20000)).cuda()
+    amps = torch.from_numpy(ph.complex_gaussian(rng, 20000)).to(torch.complex64).cuda()
+    eta.view(-1)[pts] += amps
+    s = plan.forward(eta)
+    y = s + 0.05 * float(s.abs().max()) * torch.randn_like(s)
+    del eta, s
+    L = plan.lipschitz(iters=30, seed=0)
+    lam = 0.05 * plan.lambda_max(y)
+    out = torch.empty((ny, nx, nk), dtype=torch.complex64, device="cuda")
+    plan.fista(y, lam, 2, L=L, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = plan.fista(y, lam, iters, L=L, out=out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    plan.timing(True)
+    plan.fista(y, lam, iters, L=L, out=out)
+    passes = plan.timing(False)
+    n = ny * nx * nk
+    half = ny * (nx // 2 + 1) * nk
+    # algorithmic bytes per iteration: y transforms (2 x 2 full complex passes), NUFFT forward
+    # (read 1 full + 1 half, write 1 half), adjoint (read 1 half, write 1 full), update (5 full)
+    ibytes = 8 * (4 * n + (n + 2 * half) + (half + n) + 5 * n)
+    plan.close()
+    per_pass = {k: {"avg_us": round(1e3 * ms / c, 2), "launches": c} for k, (ms, c) in passes.items() if c}
+    return {
+        "workload": "volume 256x256x2048 (ny x nx x nk), 20000 scatterers + 3 curved layers, synthetic",
+        "fista_iters": iters, "status": res.status,
+        "fista_iter_per_s": round(iters / dt, 2),
+        "ms_per_iter": round(1e3 * dt / iters, 3),
+        "algorithmic_bytes_per_iter": ibytes,
+        "hbm_GBps": round(ibytes * iters / dt / 1e9, 1),
+        "hbm_frac": round(ibytes * iters / dt / 1e9 / HBM_PEAK_GBS, 4),
+        "passes": per_pass,
+    }
+
+
 def main() -> int:
     args = parse()
     if args.gpus != 1:
@@ -323,6 +380,7 @@ def main() -> int:
     iter_bytes = sum(nbytes[k] for k in ("nufft_fwd", "nufft_adj", "fista_update"))
 
     batched = None if args.no_batch else batch_leg(P, torch, args.batch_iters)
+    volume = None if args.no_volume else volume_leg(P, torch, args.volume_iters)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -354,6 +412,7 @@ def main() -> int:
                           "frac": round(iter_bytes * args.steps / wall / 1e9 / HBM_PEAK_GBS, 4)},
         "passes": per_pass,
         "batched": batched,
+        "volume": volume,
         "cpu_baseline": cpu,
         "gpu": torch.cuda.get_device_name(0),
     }
