@@ -28,7 +28,7 @@ hipError_t lat_c2c(const isam_plan_s* p, const float2* in, float2* out, int sign
 // y transform of a volume: length ny over ncols columns (row-major [ny][ncols] <-> blocked).
 hipError_t lat_c2c_y(const isam_plan_s* p, const float2* in, float2* out, int ncols, int sign, hipStream_t s) {
     // wide tiles (16 lanes, 128 bytes per row) up to 512 rows: the rows are far apart in memory
-    ISAM_LAT_DISPATCH(p->ny, p->lat_cy, (N <= 512 ? 16 : ISAM_LAT_DEF_C),
+    ISAM_LAT_DISPATCH(p->ny, p->lat_cy, (N <= 256 ? 32 : N <= 512 ? 16 : ISAM_LAT_DEF_C),
                       return (launch_c2c<N, C>(in, out, ncols, p->twY[LatCfg<N, C>::L], sign, s, 1, 0u, 0u)));
 }
 
