@@ -82,7 +82,7 @@ ISAM_DEV float2 weight(const float2* wt, float tau, int jj) {
     const float tp = tau * kPieces;
     const int p = min((int)tp, kPieces - 1);
     const float x = tp - (float)p;
-    const float4* row = reinterpret_cast<const float4*>(wt + (p * kJ + jj) * 4);
+    const float4* row = reinterpret_cast<const float4*>(wt + p * kWtabPiece + jj * 4);
     const float4 a = row[0], b = row[1];     // (c0, c1), (c2, c3)
     float2 w;
     w.x = fmaf(fmaf(fmaf(b.z, x, b.x), x, a.z), x, a.x);
@@ -381,7 +381,7 @@ ISAM_DEV void nufft_adj_body(const float2* __restrict__ rh, float2* __restrict__
             const float tp = tau * kPieces;
             const int p = min((int)tp, kPieces - 1);
             const float xl = tp - (float)p;
-            const float4* rowp = reinterpret_cast<const float4*>(wt + p * kJ * 4);
+            const float4* rowp = reinterpret_cast<const float4*>(wt + p * kWtabPiece);
 #pragma unroll
             for (int jj = 0; jj < kJ; ++jj) {
                 const float4 ca = rowp[2 * jj], cb = rowp[2 * jj + 1];

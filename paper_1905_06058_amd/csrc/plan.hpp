@@ -27,7 +27,10 @@ namespace isam {
 
 constexpr int kJ = 6;             // interpolation taps (the only J built)
 constexpr int kPieces = 32;       // piecewise-cubic pieces of the min-max weight table over tau in [0,1)
-constexpr int kWtabEntries = kPieces * kJ * 4;   // float2 coefficients c0..c3 per piece and tap
+// float2 coefficients c0..c3 per tap; a piece's 6 taps are followed by 2 pad entries (26 float2 =
+// 52 dwords per piece, so lanes reading different pieces hit different LDS banks)
+constexpr int kWtabPiece = kJ * 4 + 2;
+constexpr int kWtabEntries = kPieces * kWtabPiece;
 constexpr int kRedSlots = 8;      // scalars per workgroup in reduction partials
 
 // Columns of one forward-NUFFT workgroup.  mode 0: a and b are Hermitian partners

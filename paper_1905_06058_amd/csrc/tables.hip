@@ -222,9 +222,10 @@ __global__ void k_minmax_fit(FitArgs a) {
                 cr += a.vinv[q * 4 + node] * ur[node][r];
                 ci += a.vinv[q * 4 + node] * ui[node][r];
             }
-            a.wtab[(p * kJ + r) * 4 + q] = make_float2((float)cr, (float)ci);
+            a.wtab[p * kWtabPiece + r * 4 + q] = make_float2((float)cr, (float)ci);
         }
     }
+    for (int e = kJ * 4; e < kWtabPiece; ++e) a.wtab[p * kWtabPiece + e] = make_float2(0.f, 0.f);
 }
 
 // Chebyshev nodes of [0, 1] and the inverse of their Vandermonde matrix (Gauss-Jordan, FP64).
