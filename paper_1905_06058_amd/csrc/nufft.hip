@@ -330,7 +330,7 @@ ISAM_DEV void nufft_adj_body(const float2* __restrict__ rh, float2* __restrict__
     __shared__ int s_red[T / 64];
     float2* wt = smem;
     float2* Y = smem + kWtabEntries;                                  // Y'[g], then the FFT tile
-    float2* SL = reinterpret_cast<float2*>(reinterpret_cast<char*>(Y) + Cf::YBUF);   // [SLOTC][3]
+    float2* SL = reinterpret_cast<float2*>(reinterpret_cast<char*>(Y) + Cf::YBUF);   // [3][SLOTC]
     const int tid = threadIdx.x;
     // Column order 0, 1, nx-1, 2, nx-2, ..., nx/2 placed XCD by XCD: both columns of a
     // half-spectrum row and the neighbouring rows (which share cache lines in the blocked
@@ -377,7 +377,7 @@ ISAM_DEV void nufft_adj_body(const float2* __restrict__ rh, float2* __restrict__
         const bool any = cbase != 0x7fffffff;
         if (prop) {
             // cell g0 + 1 + j (relative to cbase + 1), slot j / 2
-            float2* dst = SL + 3 * (fl - kJ / 2 - cbase);
+            float2* dst = SL + (fl - kJ / 2 - cbase);
             const float tp = tau * kPieces;
             const int p = min((int)tp, kPieces - 1);
             const float xl = tp - (float)p;
@@ -388,13 +388,13 @@ ISAM_DEV void nufft_adj_body(const float2* __restrict__ rh, float2* __restrict__
                 float2 w;
                 w.x = fmaf(fmaf(fmaf(cb.z, xl, cb.x), xl, ca.z), xl, ca.x);
                 w.y = fmaf(fmaf(fmaf(cb.w, xl, cb.y), xl, ca.w), xl, ca.y);
-                dst[3 * jj + (jj >> 1)] = cfmac(w, vn, c2(0.f, 0.f));
+                dst[(jj >> 1) * Cf::SLOTC + jj] = cfmac(w, vn, c2(0.f, 0.f));
             }
         }
         __syncthreads();
         if (any) {
             for (int c = tid; c < Cf::SLOTC; c += T) {
-                const float2 s0 = SL[3 * c], s1 = SL[3 * c + 1], s2 = SL[3 * c + 2];
+                const float2 s0 = SL[c], s1 = SL[Cf::SLOTC + c], s2 = SL[2 * Cf::SLOTC + c];
                 const int g = (cbase + 1 + c) & (K - 1);
                 Y[g] = cadd(Y[g], cadd(cadd(s0, s1), s2));
             }
