@@ -103,14 +103,12 @@ ISAM_DEV float2 modulation(const NufftArgs& a, float2 En, float Bl, double t) {
     return e;
 }
 
+// Oversampled depth spectrum Y of column col into buf (natural order plus the J-entry wrap
+// halo), by the K-point LDS FFT; ends with a barrier.
 template <int K>
-ISAM_DEV void forward_column(const NufftArgs& a, const float2* __restrict__ etahat, int col, float2* buf,
-                             const float2* wt, float2 (&xt)[NuCfg<K>::NPT], int tid) {
+ISAM_DEV void fft_column(const NufftArgs& a, const float2* __restrict__ etahat, int col, float2* buf, int tid) {
     using Cf = NuCfg<K>;
     using F = typename Cf::Fwd;
-    float2 en[Cf::NPT];                     // e^{i phi} e^{2 i k z_f} / sqrt(nz) of the thread's samples
-#pragma unroll
-    for (int r = 0; r < Cf::NPT; ++r) en[r] = a.En[min(tid + r * Cf::T, a.nk - 1)];
     float2 v[F::EPT];
 #pragma unroll
     for (int i = 0; i < F::BPTO; ++i) {
@@ -142,6 +140,17 @@ ISAM_DEV void forward_column(const NufftArgs& a, const float2* __restrict__ etah
         }
     }
     __syncthreads();
+}
+
+// The thread's samples n = tid + r T of column col: J-tap interpolation of Y (in buf) at the
+// Stolt points, times the modulation.
+template <int K>
+ISAM_DEV void gather_column(const NufftArgs& a, int col, const float2* buf, const float2* wt,
+                            float2 (&xt)[NuCfg<K>::NPT], int tid) {
+    using Cf = NuCfg<K>;
+    float2 en[Cf::NPT];                     // e^{i phi} e^{2 i k z_f} / sqrt(nz) of the thread's samples
+#pragma unroll
+    for (int r = 0; r < Cf::NPT; ++r) en[r] = a.En[min(tid + r * Cf::T, a.nk - 1)];
     const double q2 = a.q2[col];
     const float Bl = a.Bl[col];
 #pragma unroll
@@ -186,9 +195,63 @@ ISAM_DEV void nufft_fwd_body(const float2* __restrict__ etahat, const float2* __
     const int b = xcd_tile(bidx, nblk);                // neighbouring pairs on one XCD
     const FwdPair pr = a.pairs[b];
     const int col = half == 0 || pr.mode == 2 ? pr.a : pr.b;
-    float2 xt[Cf::NPT];
-    forward_column<K>(a, etahat, col, buf, wt, xt, tid);
+    fft_column<K>(a, etahat, col, buf, tid);
     const int nh = a.nhalf;
+    float acc[1] = {0.f};
+    if (pr.mode == 0) {
+        // Partners a, b = -a share q^2, hence the Stolt points, weights and modulation: each
+        // of the 2T threads interpolates its samples of both columns with one set of weights
+        // and forms the Hermitian combination at once.
+        constexpr int T2 = 2 * Cf::T;
+        constexpr int NP2 = (Cf::NK + T2 - 1) / T2;
+        const int j = threadIdx.x;
+        float2 en[NP2], ya[NP2], yb[NP2];
+#pragma unroll
+        for (int r = 0; r < NP2; ++r) {
+            const int n = min(j + r * T2, a.nk - 1);
+            en[r] = a.En[n];
+            ya[r] = yhat ? yhat[blk(pr.ha, n, nh)] : c2(0.f, 0.f);
+            yb[r] = yhat && pr.hb >= 0 ? yhat[blk(pr.hb, n, nh)] : c2(0.f, 0.f);
+        }
+        const double q2 = a.q2[pr.a];
+        const float Bl = a.Bl[pr.a];
+        const float2* bufA = smem;
+        const float2* bufB = smem + Cf::BUF;
+#pragma unroll
+        for (int r = 0; r < NP2; ++r) {
+            const int n = j + r * T2;
+            if (n >= a.nk) continue;
+            float2 xa = c2(0.f, 0.f), xb = c2(0.f, 0.f);
+            double t;
+            int fl;
+            float tau;
+            if (stolt_point(a, q2, n, t, fl, tau)) {
+                const int g = (fl - kJ / 2 + 1) & (K - 1);               // tap j = 1 at g0 + 1
+                float2 sa = c2(0.f, 0.f), sb = c2(0.f, 0.f);
+#pragma unroll
+                for (int jj = 0; jj < kJ; ++jj) {
+                    const float2 w = weight(wt, tau, jj);
+                    sa = cfma(w, bufA[g + jj], sa);
+                    sb = cfma(w, bufB[g + jj], sb);
+                }
+                const float2 m = modulation(a, en[r], Bl, t);
+                xa = cmul(sa, m);
+                xb = cmul(sb, m);
+            }
+            const float2 zc = cscale(cadd(xa, cconj(xb)), 0.5f);
+            const float2 z = csub(zc, ya[r]);
+            zh[blk(pr.ha, n, nh)] = z;
+            if (pr.hb >= 0) {                          // both stored: Z[b] = conj Z[a]
+                const float2 z1 = csub(cconj(zc), yb[r]);
+                zh[blk(pr.hb, n, nh)] = z1;
+                acc[0] += cabs2(z) + cabs2(z1);
+            } else {
+                acc[0] += 2.f * cabs2(z);
+            }
+        }
+    } else {
+    float2 xt[Cf::NPT];
+    gather_column<K>(a, col, buf, wt, xt, tid);
     float2 yh[Cf::NPT], yh1[Cf::NPT];
 #pragma unroll
     for (int r = 0; r < Cf::NPT; ++r) {
@@ -205,7 +268,6 @@ ISAM_DEV void nufft_fwd_body(const float2* __restrict__ etahat, const float2* __
         }
     }
     __syncthreads();
-    float acc[1] = {0.f};
     if (half == 0) {
         const float2* other = smem + Cf::BUF;
 #pragma unroll
@@ -235,6 +297,7 @@ ISAM_DEV void nufft_fwd_body(const float2* __restrict__ etahat, const float2* __
                 }
             }
         }
+    }
     }
     if (partials) {
         __syncthreads();
@@ -282,7 +345,8 @@ __global__ __launch_bounds__(2 * NuCfg<K>::T) void k_nufft_calgrad(const float2*
     const bool active = half == 0 || pr.mode != 2;
     const int col = half == 0 || pr.mode == 2 ? pr.a : pr.b;
     float2 xt[Cf::NPT];
-    forward_column<K>(a, etahat, col, buf, wt, xt, tid);
+    fft_column<K>(a, etahat, col, buf, tid);
+    gather_column<K>(a, col, buf, wt, xt, tid);
     const int nh = a.nhalf;
     // column b of a partner pair with no stored row has G[b] = conj G[a]
     const bool mirrored = half == 1 && pr.hb < 0;
