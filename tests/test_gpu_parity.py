@@ -212,6 +212,31 @@ def test_fista_tiny_fixed_iterations(P):
     assert abs(res.resid2 - ref.resid2[-1]) < 1e-4 * ref.resid2[-1]
 
 
+def test_bscan_fista_200_iterations_lowers_the_objective(P):
+    """Full 1024 x 2048 workload, 200 iterations: at this size the oracle cannot run the solve,
+    so the check is a property of Alg. 1: the Eq. 12 objective, evaluated with the (parity-
+    tested) forward operator, falls from F(0) to F(z^20) to F(z^200)."""
+    import torch
+    w = ph.workload("bscan")
+    with make_plan(P, w.optics) as plan:
+        eta = to_dev(ph.phantom(w))
+        y = to_dev(ph.add_noise(to_host(plan.forward(eta)), w.snr_db, w.seed))
+        L = plan.lipschitz(iters=50, seed=0)
+        lam = w.lam_frac * plan.lambda_max(y)
+
+        def objective(z):
+            r = (plan.forward(z) - y).double()
+            return 0.5 * float((r * r).sum()) + lam * float(z.abs().double().sum())
+
+        f0 = 0.5 * float((y.double() ** 2).sum())
+        r20 = plan.fista(y, lam, 20, L=L)
+        f20 = objective(r20.eta)
+        r200 = plan.fista(y, lam, 200, L=L)
+        f200 = objective(r200.eta)
+    assert r200.status == 0 and math.isfinite(r200.resid2)
+    assert f200 < f20 < f0
+
+
 def test_fista_device_stop_leaves_the_stopping_iterate(P):
     """Eq. 15 is checked on the device every iteration; after it holds the solver kernels
     return at once, so the image equals a fixed-count run of the reported length."""
