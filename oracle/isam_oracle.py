@@ -503,6 +503,22 @@ class VolumeOperator:
         out /= math.sqrt(g.nk)
         return np.fft.ifft2(out.reshape(g.ny, g.nx, g.nk), axes=(0, 1), norm="ortho")
 
+    def calibration_gradient(self, eta, grad_s) -> np.ndarray:
+        """Gradient of <grad_s, A eta> with respect to (a2, a3, z_focus) for a volume.
+
+        As for a B-scan (calibration_gradient): d/dtheta = Re sum conj(F grad_s) (i D_theta c X)
+        with F the two-dimensional unitary lateral DFT and D = ((k-k0)^2, (k-k0)^3, 2k - kz).
+        """
+        g = self.g
+        G = grids(g)
+        eta_hat = np.fft.fft2(np.asarray(eta, np.complex128), axes=(0, 1), norm="ortho")
+        X = self._resample(eta_hat.reshape(g.ny * g.nx, g.nk))
+        Gs = np.fft.fft2(np.asarray(grad_s, np.float64).astype(np.complex128), axes=(0, 1), norm="ortho")
+        base = np.conj(Gs.reshape(g.ny * g.nx, g.nk)) * 1j * self.c * X
+        d = (G.k - G.kc)[None, :]
+        derivs = (np.broadcast_to(d ** 2, base.shape), np.broadcast_to(d ** 3, base.shape), 2 * G.k[None, :] - self.kz)
+        return np.array([float(np.sum(np.real(base * D))) for D in derivs])
+
 
 # --------------------------------------------------------------------------- calibration
 

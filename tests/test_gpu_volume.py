@@ -50,6 +50,20 @@ def test_volume_forward_adjoint_match_oracle(P, ny, nx, nk):
     assert rel(a, V.AH(r)) < TOL_OP
 
 
+def test_volume_calibration_grad_matches_oracle(P):
+    ny, nx, nk = 4, 16, 64
+    o, dy = vol_optics(nx, ny, nk, dy=5e-6, focus=9)
+    g = O.Geometry.of(o, ny=ny, dy=dy)
+    rng = np.random.default_rng(6)
+    eta = ph.complex_gaussian(rng, (ny, nx, nk))
+    G = rng.standard_normal((ny, nx, nk))
+    ref = O.VolumeOperator(g, "N").calibration_gradient(eta, G)
+    with P.Plan(P.Geometry.of(o, ny=ny, dy=dy)) as plan:
+        got = plan.calibration_grad(to_dev(eta), to_dev(G))
+    for i in range(3):
+        assert abs(got[i] - ref[i]) <= 2e-4 * abs(ref[i]), (i, got[i], ref[i])
+
+
 def test_volume_fista_matches_oracle(P):
     ny, nx, nk = 8, 16, 64
     o, dy = vol_optics(nx, ny, nk, dy=4e-6)

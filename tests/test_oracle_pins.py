@@ -325,6 +325,21 @@ def test_volume_adjoint_and_transpose_symmetry(mode):
     assert np.abs(sw - np.swapaxes(Ax, 0, 1)).max() < 1e-12 * np.abs(Ax).max()
 
 
+@pytest.mark.parametrize("mode", ["E", "N"])
+def test_volume_calibration_gradient_matches_central_differences(mode):
+    g, _ = _vol(8, 4, 32, dy=5e-6)
+    rng = np.random.default_rng(15)
+    x = ph.complex_gaussian(rng, (4, 8, 32))
+    G = rng.standard_normal((4, 8, 32))
+    an = O.VolumeOperator(g, mode).calibration_gradient(x, G)
+    for i, name in enumerate(("a2", "a3", "z_focus")):
+        v = getattr(g, name)
+        h = 1e-5 * abs(v)
+        fp = np.sum(G * O.VolumeOperator(g.with_(**{name: v + h}), mode).A(x))
+        fm = np.sum(G * O.VolumeOperator(g.with_(**{name: v - h}), mode).A(x))
+        assert abs(an[i] - (fp - fm) / (2 * h)) < 1e-6 * abs(an[i]), name
+
+
 def test_volume_nufft_close_to_exact():
     g, _ = _vol(8, 4, 64, dy=5e-6)
     rng = np.random.default_rng(14)
