@@ -31,7 +31,8 @@
  *   object eta    complex64 interleaved (re, im) float pairs, [ny][nx][nk], depth contiguous
  *   spectra s, y  float32 [ny][nx][nk], k contiguous
  *   weights w     float32 [ny][nx][nk] (same layout as eta), or NULL for w = 1
- * (ny = 1 for a B-scan: [nx][nk].)
+ * (ny = 1 for a B-scan: [nx][nk].)  Shapes written [nx][nk] below mean [ny][nx][nk]
+ * for a volume.
  *
  * Every entry point returns ISAM_OK (0) or a negative ISAM_E* code; none aborts
  * or throws.  Work is enqueued on the given HIP stream (a hipStream_t passed as
