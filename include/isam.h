@@ -231,8 +231,9 @@ int isam_batch_fista(isam_batch_t b, const float* y, const float* lambda, const 
 
 /* Autotuner: for every group of scans with nx >= 192, times the batched update
  * pass (complex tiles) and R2C pass (real tiles) at tile widths 2, 4 and 8
- * lanes, `reps` launches each, and keeps the fastest.  Clobbers the scans'
- * solver workspaces (not their tables); synchronises. */
+ * lanes, `reps` launches each, and keeps the fastest.  Waits for earlier work on
+ * `stream`, clobbers the scans' solver workspaces (not their tables) and
+ * synchronises. */
 int isam_batch_tune(isam_batch_t b, int reps, void* stream);
 
 /* Tile widths in use: for up to cap lateral groups, nx and the lanes per tile of
@@ -241,7 +242,8 @@ int isam_batch_tiles(isam_batch_t b, int32_t* nx, int32_t* sel_c, int32_t* sel_r
                      int32_t* ngroups);
 
 /* Set the tile widths (lanes: 1, 2, 4 or 8) of the group with lateral length nx,
- * e.g. from a saved tuning.  EINVAL if no group has that nx. */
+ * e.g. from a saved tuning.  Synchronises the device.  EINVAL if no group has
+ * that nx. */
 int isam_batch_set_tiles(isam_batch_t b, int32_t nx, int32_t sel_c, int32_t sel_r);
 
 /* Release a batch and its plans (NULL is allowed). */

@@ -576,7 +576,8 @@ extern "C" int isam_batch_fista(isam_batch_t b, const float* y, const float* lam
 
 extern "C" int isam_batch_tune(isam_batch_t b, int reps, void* stream) {
     if (!b || reps < 1) return ISAM_EINVAL;
-    (void)stream;
+    // the timed passes reuse the scans' workspaces: earlier work on the caller's stream must be done
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return ISAM_EHIP;
     hipStream_t s = b->cs;
     // the timed passes run on the scans' own workspaces: clear them (no graph is being captured)
     for (isam_plan_t p : b->plans) {
@@ -660,6 +661,8 @@ extern "C" int isam_batch_set_tiles(isam_batch_t b, int32_t nx, int32_t sel_c, i
     if (!b) return ISAM_EINVAL;
     for (Group& g : b->lat)
         if (g.key == nx) {
+            // the block maps are rewritten in place: no earlier work may still read them
+            if (hipDeviceSynchronize() != hipSuccess) return ISAM_EHIP;
             g.sel_c = sel_c;
             g.sel_r = sel_r;
             for (int i : g.scans) {
