@@ -59,7 +59,9 @@ struct NuAdjCfg {
     using Adj = LdsFft<K, 1, T, -1, 1, L>;
     static constexpr size_t YBUF = (size_t)lds_size(K) * sizeof(float2);
     static constexpr size_t SLOTS = (size_t)3 * SLOTC * sizeof(float2);
-    static constexpr size_t LDS = (size_t)kWtabEntries * sizeof(float2) + YBUF + SLOTS;
+    // Y' accumulates in registers (each thread owns the cells its FFT butterflies start from),
+    // so the slot arrays and the FFT tile share one LDS region
+    static constexpr size_t LDS = (size_t)kWtabEntries * sizeof(float2) + (YBUF > SLOTS ? YBUF : SLOTS);
     static_assert(SLOTC < K, "a chunk's cells map to distinct oversampled cells");
 };
 
@@ -393,8 +395,8 @@ ISAM_DEV void nufft_adj_body(const float2* __restrict__ rh, float2* __restrict__
     extern __shared__ float2 smem[];
     __shared__ int s_red[T / 64];
     float2* wt = smem;
-    float2* Y = smem + kWtabEntries;                                  // Y'[g], then the FFT tile
-    float2* SL = reinterpret_cast<float2*>(reinterpret_cast<char*>(Y) + Cf::YBUF);   // [3][SLOTC]
+    float2* Y = smem + kWtabEntries;                                  // the FFT tile
+    float2* SL = Y;                                                   // [3][SLOTC] (same region)
     const int tid = threadIdx.x;
     // Column order 0, 1, nx-1, 2, nx-2, ..., nx/2 placed XCD by XCD: both columns of a
     // half-spectrum row and the neighbouring rows (which share cache lines in the blocked
@@ -405,7 +407,6 @@ ISAM_DEV void nufft_adj_body(const float2* __restrict__ rh, float2* __restrict__
     const bool conj_in = ce.y < 0;
     const int row = conj_in ? -1 - ce.y : ce.y;
     for (int i = tid; i < kWtabEntries; i += T) wt[i] = a.wtab[i];
-    for (int i = tid; i < K; i += T) Y[i] = c2(0.f, 0.f);
     const double q2 = a.q2[col];
     const float Bl = a.Bl[col];
     // residual spectrum and modulation of the thread's samples, fetched up front
@@ -416,6 +417,10 @@ ISAM_DEV void nufft_adj_body(const float2* __restrict__ rh, float2* __restrict__
         xr[ch] = rh[blk(row, n, a.nhalf)];
         en[ch] = a.En[n];
     }
+    // Y'[x] for the cells x = b + j K / RO this thread starts the inverse FFT from
+    float2 v[F::EPT];
+#pragma unroll
+    for (int e = 0; e < F::EPT; ++e) v[e] = c2(0.f, 0.f);
     for (int ch = 0; ch < Cf::NCH; ++ch) {
         const int n = ch * Cf::CS + tid;
         const bool mine = tid < Cf::CS;
@@ -457,24 +462,25 @@ ISAM_DEV void nufft_adj_body(const float2* __restrict__ rh, float2* __restrict__
         }
         __syncthreads();
         if (any) {
-            for (int c = tid; c < Cf::SLOTC; c += T) {
-                const float2 s0 = SL[c], s1 = SL[Cf::SLOTC + c], s2 = SL[2 * Cf::SLOTC + c];
-                const int g = (cbase + 1 + c) & (K - 1);
-                Y[g] = cadd(Y[g], cadd(cadd(s0, s1), s2));
+            // cell x of this thread sits at c = x - (cbase + 1) (mod K) of the chunk's slots
+#pragma unroll
+            for (int i = 0; i < F::BPTO; ++i) {
+                int cc, b;
+                if (F::outer(tid, i, cc, b)) {
+#pragma unroll
+                    for (int j = 0; j < Cf::RO; ++j) {
+                        const int c = (b + j * Cf::SPAN - cbase - 1) & (K - 1);
+                        if (c < Cf::SLOTC) {
+                            const float2 s0 = SL[c], s1 = SL[Cf::SLOTC + c], s2 = SL[2 * Cf::SLOTC + c];
+                            v[i * Cf::RO + j] = cadd(v[i * Cf::RO + j], cadd(cadd(s0, s1), s2));
+                        }
+                    }
+                }
             }
         }
         __syncthreads();
     }
-    float2 v[F::EPT];
-#pragma unroll
-    for (int i = 0; i < F::BPTO; ++i) {
-        int cc, b;
-        if (F::outer(tid, i, cc, b)) {
-#pragma unroll
-            for (int j = 0; j < Cf::RO; ++j) v[i * Cf::RO + j] = Y[b + j * Cf::SPAN];
-        }
-    }
-    F::run(v, Y, a.tw8, tid);         // opens with a barrier: the reads of Y above are done
+    F::run(v, Y, a.tw8, tid);         // opens with a barrier: the last reads of the slots are done
 #pragma unroll
     for (int i = 0; i < F::BPTO; ++i) {
         int cc, b;
