@@ -220,9 +220,12 @@ ISAM_DEV float2 twiddle(const float2* tw, int e) {
     return SIGN > 0 ? cconj(w) : w;
 }
 
-template <int N, int C, int T, int SIGN, int LS = C, int L = 4>
+// PS: one LDS pad slot per 2^PS elements (lds_pad uses PS = 4).
+template <int N, int C, int T, int SIGN, int LS = C, int L = 4, int PS = 4>
 struct LdsFft {
     static_assert(fft_length_ok(N, L), "unsupported transform length");
+    ISAM_DEV static constexpr int pad(int e) { return e + (e >> PS); }
+    static constexpr int SIZE = N * LS + ((N * LS) >> PS) + 1;   // LDS entries used
     static constexpr int NP = fft_np(N, L);
     static constexpr int RO = fft_radix(N, 0, L);
     static constexpr int NBO = N / RO * C;                  // butterflies in an outer pass
@@ -252,7 +255,7 @@ struct LdsFft {
                 if ((NB % T == 0) || f < NB) {
                     const int c = f % C, b = f / C;
 #pragma unroll
-                    for (int j = 0; j < R; ++j) x[i * R + j] = lds[lds_pad((b + j * (N / R)) * LS + c)];
+                    for (int j = 0; j < R; ++j) x[i * R + j] = lds[pad((b + j * (N / R)) * LS + c)];
                 }
             }
             __syncthreads();
@@ -269,7 +272,7 @@ struct LdsFft {
                     Dft<R, SIGN>::run(&x[i * R]);
                     const int base = (b - k) * R + k;
 #pragma unroll
-                    for (int j = 0; j < R; ++j) lds[lds_pad((base + j * NS) * LS + c)] = x[i * R + j];
+                    for (int j = 0; j < R; ++j) lds[pad((base + j * NS) * LS + c)] = x[i * R + j];
                 }
             }
             __syncthreads();
@@ -297,7 +300,7 @@ struct LdsFft {
                 if (outer(tid, i, c, b)) {
                     Dft<RO, SIGN>::run(&v[i * RO]);
 #pragma unroll
-                    for (int j = 0; j < RO; ++j) lds[lds_pad((b * RO + j) * LS + c)] = v[i * RO + j];
+                    for (int j = 0; j < RO; ++j) lds[pad((b * RO + j) * LS + c)] = v[i * RO + j];
                 }
             }
             __syncthreads();
@@ -308,7 +311,7 @@ struct LdsFft {
                 int c, b;
                 if (outer(tid, i, c, b)) {
 #pragma unroll
-                    for (int j = 0; j < RO; ++j) v[i * RO + j] = lds[lds_pad((b + j * SPAN) * LS + c)];
+                    for (int j = 0; j < RO; ++j) v[i * RO + j] = lds[pad((b + j * SPAN) * LS + c)];
                 }
             }
 #pragma unroll

@@ -56,8 +56,8 @@ struct NuAdjCfg {
     static constexpr int CS = T < NK / 4 ? T : NK / 4;            // samples per chunk
     static constexpr int NCH = NK / CS;                             // chunks
     static constexpr int SLOTC = 2 * CS + CS / 8 + 16;             // cells of one chunk
-    using Adj = LdsFft<K, 1, T, -1, 1, L>;
-    static constexpr size_t YBUF = (size_t)lds_size(K) * sizeof(float2);
+    using Adj = LdsFft<K, 1, T, -1, 1, L, 6>;       // sparser padding: the tile fits 4 workgroups per CU
+    static constexpr size_t YBUF = (size_t)Adj::SIZE * sizeof(float2);
     static constexpr size_t SLOTS = (size_t)3 * SLOTC * sizeof(float2);
     // Y' accumulates in registers (each thread owns the cells its FFT butterflies start from),
     // so the slot arrays and the FFT tile share one LDS region
