@@ -226,10 +226,12 @@ __global__ __launch_bounds__((LatCfg<N, C>::T)) void k_lat_r2c_batch(const LatSc
 }
 
 // Weighted complex soft threshold of Eq. 14 with threshold theta (theta = 0: identity).
+// The hardware square root and reciprocal (about 1 ulp) replace the correctly rounded
+// library forms, whose range scaling and division fix-ups cost more than the transform.
 ISAM_DEV float2 soft_threshold(float2 u, float theta) {
-    const float mag = sqrtf(u.x * u.x + u.y * u.y);
+    const float mag = __builtin_amdgcn_sqrtf(u.x * u.x + u.y * u.y);
     const float sh = fmaxf(mag - theta, 0.f);
-    const float f = theta > 0.f ? sh / (sh + theta) : 1.f;
+    const float f = theta > 0.f ? sh * __builtin_amdgcn_rcpf(sh + theta) : 1.f;
     return cscale(u, f);
 }
 
@@ -297,7 +299,7 @@ ISAM_DEV void lat_fista_body(float2* __restrict__ eta_hat, const float2* __restr
                     acc[1] += cabs2(g);
                     acc[2] += cabs2(csub(zn, u));               // z - eta + g
                 }
-                acc[3] += wt * sqrtf(cabs2(zn));
+                acc[3] += wt * __builtin_amdgcn_sqrtf(cabs2(zn));
                 v[i * RO + j] = cadd(zn, cscale(csub(zn, zp), fs.beta));   // next momentum point
             }
         }
