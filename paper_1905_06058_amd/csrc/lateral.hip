@@ -34,16 +34,16 @@ hipError_t lat_c2c_y(const isam_plan_s* p, const float2* in, float2* out, int nc
 
 int lat_blocks(const isam_plan_s* p, int kind) {
     if (kind == 0) {
-        ISAM_LAT_SWITCH(return p->ny * (p->nk / C));
+        ISAM_LAT_SWITCH((void)N; return p->ny * (p->nk / C));
     }
-    ISAM_LAT_SWITCH_R(return p->ny * (p->nk / (2 * C)));
+    ISAM_LAT_SWITCH_R((void)N; return p->ny * (p->nk / (2 * C)));
 }
 
 int lat_tile(int nx, int sel, int real) {
     if (real) {
-        ISAM_LAT_DISPATCH(nx, sel, ISAM_LAT_DEF_CR, return C);
+        ISAM_LAT_DISPATCH(nx, sel, ISAM_LAT_DEF_CR, (void)N; return C);
     }
-    ISAM_LAT_DISPATCH(nx, sel, ISAM_LAT_DEF_C, return C);
+    ISAM_LAT_DISPATCH(nx, sel, ISAM_LAT_DEF_C, (void)N; return C);
 }
 
 int lat_radix_cap(int nx, int sel, int real) {

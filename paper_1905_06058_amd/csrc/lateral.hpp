@@ -111,7 +111,7 @@ ISAM_DEV float2 hermitian_pair(const float2* zh, int x, int col) {
 // Split the transform F of (ra + i rb) into the half spectra of ra and rb through LDS.
 template <int N, int T, int C, int L>
 ISAM_DEV void split_store(float2* lds, const float2 (&v)[LdsFft<N, C, T, -1, C, L>::EPT], float2* rh,
-                          int nk, int n0, float scale) {
+                          int /*nk*/, int n0, float scale) {
     using F = LdsFft<N, C, T, -1, C, L>;
     constexpr int RO = F::RO, SPAN = F::SPAN;
     __syncthreads();
@@ -237,7 +237,7 @@ ISAM_DEV float2 soft_threshold(float2 u, float theta) {
 
 template <int N, int C, bool NORMS>
 ISAM_DEV void lat_fista_body(float2* __restrict__ eta_hat, const float2* __restrict__ ghat,
-                             float2* __restrict__ z, const float* __restrict__ w, int nk,
+                             float2* __restrict__ z, const float* __restrict__ w, int /*nk: blocked*/,
                              const float2* __restrict__ tw, float scale, const FistaStep& fs,
                              float* __restrict__ partials, int tile, int ntiles) {
     using Cf = LatCfg<N, C>;

@@ -22,8 +22,6 @@ using namespace isam;
 
 namespace {
 
-constexpr double kPi = 3.14159265358979323846;
-
 // FP64 sums (or maxima) of the per-workgroup partials: strided per-thread sums, then a
 // fixed-order tree, so the result does not depend on scheduling.
 __global__ __launch_bounds__(256) void k_finalize(const float* __restrict__ partials, int nblocks,

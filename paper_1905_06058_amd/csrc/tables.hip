@@ -133,7 +133,7 @@ __global__ void k_minmax_sums(SumArgs a) {
     sim[threadIdx.x] = im;
     __syncthreads();
     for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
+        if ((int)threadIdx.x < w) {
             sre[threadIdx.x] += sre[threadIdx.x + w];
             sim[threadIdx.x] += sim[threadIdx.x + w];
         }
