@@ -205,9 +205,8 @@ int isam_batch_plan(const isam_geometry* geoms, int nscans, void* stream, isam_b
 int isam_batch_offsets(isam_batch_t b, int64_t* offsets);
 
 /* The plan of scan i (owned by the batch; valid until isam_batch_destroy).  Its
- * single-scan calls use the same tables and tile widths as the batch.  Change
- * its calibration only through isam_batch_set_calibration (the batch keeps a
- * copy of the plan's NUFFT constants). */
+ * single-scan calls use the same tables and tile widths as the batch; a
+ * calibration set on it directly is picked up by the next batch call. */
 int isam_batch_scan_plan(isam_batch_t b, int i, isam_plan_t* out);
 
 /* isam_set_calibration for scan i, keeping the batch's records in step. */

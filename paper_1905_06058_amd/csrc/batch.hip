@@ -291,6 +291,21 @@ void fill_static_records(isam_batch_t b) {
 
 const int2* map_of(isam_batch_t b, const Group& g, int which) { return b->maps + g.map_off[which]; }
 
+// The scans' NUFFT constants as they are now (a scan's calibration may have changed through
+// its own plan); the stop pointers of the solver records are kept.
+void refresh_nu_args(isam_batch_t b) {
+    for (int i = 0; i < b->n; ++i) {
+        const isam::NufftArgs a = b->plans[i]->nufft_args();
+        for (auto& r : b->nurec) {
+            const int* stop = r.host[i].a.stop;
+            r.host[i].a = a;
+            r.host[i].a.stop = stop;
+        }
+    }
+}
+
+
+
 #define B_TRY(x)                                     \
     do {                                             \
         if ((x) != hipSuccess) return ISAM_EHIP;     \
@@ -449,6 +464,7 @@ extern "C" int isam_batch_forward(isam_batch_t b, const void* eta, float* s_out,
         b->latrec[LK_C2C_FWD].host[i].in = static_cast<const float2*>(eta) + b->off[i];
         b->latrec[LK_C2R].host[i].out = s_out + b->off[i];
     }
+    refresh_nu_args(b);
     int rc = b->latrec[LK_C2C_FWD].upload(s);
     rc = rc ? rc : b->latrec[LK_C2R].upload(s);
     rc = rc ? rc : b->nurec[NK_FWD_OP].upload(s);
@@ -471,6 +487,7 @@ extern "C" int isam_batch_adjoint(isam_batch_t b, const float* r, void* eta_out,
         b->latrec[LK_R2C].host[i].in = r + b->off[i];
         b->latrec[LK_C2C_INV].host[i].out = static_cast<float2*>(eta_out) + b->off[i];
     }
+    refresh_nu_args(b);
     int rc = b->latrec[LK_R2C].upload(s);
     rc = rc ? rc : b->latrec[LK_C2C_INV].upload(s);
     rc = rc ? rc : b->nurec[NK_ADJ_OP].upload(s);
@@ -503,6 +520,7 @@ extern "C" int isam_batch_fista(isam_batch_t b, const float* y, const float* lam
             if (rc) return rc;
         }
     }
+    refresh_nu_args(b);
     for (int i = 0; i < b->n; ++i) {
         isam_plan_s* p = b->plans[i];
         const int rc = isam::fista_prepare(p, y + b->off[i], w ? w + b->off[i] : nullptr, s);

@@ -133,6 +133,24 @@ def test_batch_tuner_keeps_results_consistent(P):
         assert rel(to_host(b.scan(s2, 3)), to_host(b.scan(s, 3))) < 1e-6
 
 
+def test_batch_follows_calibration_changes_of_its_scans(P):
+    import torch
+    opts = optics_list()
+    etas, _ = batch_data(opts, 4)
+    with P.Batch([P.Geometry.of(o) for o in opts]) as b:
+        eta = packed(b, etas, torch.complex64)
+        b.forward(eta)                                     # records uploaded once
+        o2 = ph.custom_optics(opts[2].nx, opts[2].nk, edge_phase2=7 * math.pi, edge_phase3=1 * math.pi,
+                              focus_rows=-9.25)
+        b.plan(2).set_calibration(o2.a2, o2.a3, o2.z_focus)          # directly on the scan's plan
+        b.set_calibration(4, o2.a2, o2.a3, 3 * o2.z_focus)           # through the batch
+        s = b.forward(eta)
+        for i in range(b.n):
+            assert bool((b.scan(s, i) == b.plan(i).forward(b.scan(eta, i).contiguous())).all()), i
+        g2 = O.Geometry.of(opts[2], a2=o2.a2, a3=o2.a3, z_focus=o2.z_focus)
+        assert rel(to_host(b.scan(s, 2)), O.forward_nufft(g2, etas[2])) < 1e-5
+
+
 def test_uneven_batch_of_sixty_four_scans(P):
     """64 scans, nx drawn from {256, 384, ..., 1024}, nk from {1024, 2048}, own optics each."""
     import torch
