@@ -256,6 +256,25 @@ def test_fista_device_stop_leaves_the_stopping_iterate(P):
     assert a.resid2 == b.resid2
 
 
+def test_fista_at_full_depth_length(P):
+    """64 A-scans of the benchmark's depth length (nk = 2048, K = 4096 NUFFT kernels) and
+    optics (40 pi / 8 pi, focus +512 rows): 30 FISTA iterations against the oracle."""
+    o = ph.custom_optics(64, 2048, edge_phase2=40 * math.pi, edge_phase3=8 * math.pi, focus_rows=512)
+    g = O.Geometry.of(o)
+    rng = np.random.default_rng(23)
+    eta = ph.layers(rng, 64, 2048, 3) + ph.point_scatterers(rng, 64, 2048, 120)
+    op = O.Operator(g, "N")
+    y = ph.add_noise(op.A(eta), 25.0, 23)
+    with make_plan(P, o) as plan:
+        L = plan.lipschitz(iters=50, seed=0)
+        lam = 0.05 * plan.lambda_max(to_dev(y))
+        res = plan.fista(to_dev(y), lam, 30, L=L)
+        z = to_host(res.eta)
+    ref = O.fista(op, y, lam, L, 30)
+    assert rel(z, ref.z) < TOL_FISTA
+    assert abs(res.resid2 - ref.resid2[-1]) < 1e-4 * ref.resid2[-1]
+
+
 def test_fista_mixed_radix_lateral_length(P):
     """384 A-scans (3 x 128): the FISTA pass runs a radix-3 lateral transform."""
     o = ph.custom_optics(384, 128, edge_phase2=20 * math.pi, edge_phase3=4 * math.pi, focus_rows=32)
