@@ -134,17 +134,19 @@ def cpu_baseline(w, sample_nx: int, budget_s: float, iters_full: int) -> dict:
     }
 
 
-def batch_leg(P, torch, iters: int) -> dict:
-    """64 B-scans of uneven size (nx from {256, 384, ..., 1024}, nk from {1024, 2048}, own
-    phantom and dispersion each): one batch (tuned tiles, captured iteration graph) against
-    the same scans run one after another through their own plans (one launch per pass per scan)."""
+def batch_leg(P, torch, iters: int, nscans: int = 64, nx_choices=tuple(range(256, 1025, 128)),
+              nk_choices=(1024, 2048), label: str = "") -> dict:
+    """B-scans of uneven size (by default 64 of them, nx from {256, 384, ..., 1024}, nk from
+    {1024, 2048}), own phantom and dispersion each: one batch (tuned tiles, captured iteration
+    graph) against the same scans run one after another through their own plans (one launch per
+    pass per scan)."""
     import numpy as np
     import phantoms as ph
     rng = np.random.default_rng(3)
     opts = []
-    for _ in range(64):
-        nx = int(rng.choice(np.arange(256, 1025, 128)))
-        nk = int(rng.choice([1024, 2048]))
+    for _ in range(nscans):
+        nx = int(rng.choice(np.array(nx_choices)))
+        nk = int(rng.choice(np.array(nk_choices)))
         opts.append(ph.custom_optics(nx, nk, edge_phase2=float(rng.uniform(10, 40)) * math.pi,
                                      edge_phase3=float(rng.uniform(-8, 8)) * math.pi,
                                      focus_rows=float(rng.uniform(-nk / 4, nk / 4))))
@@ -195,9 +197,9 @@ def batch_leg(P, torch, iters: int) -> dict:
     pts = b.total
     b.close()
     return {
-        "workload": "64 uneven B-scans, nx from {256..1024 step 128}, nk from {1024, 2048}, own phantom, "
-                    "dispersion and focus each; synthetic",
-        "scans": 64, "points": pts, "fista_iters": iters,
+        "workload": label or (f"{nscans} uneven B-scans, nx from {list(nx_choices)}, nk from {list(nk_choices)}, "
+                              "own phantom, dispersion and focus each; synthetic"),
+        "scans": nscans, "points": pts, "fista_iters": iters,
         "tiles": {str(k): v for k, v in tiles.items()},
         "batched_fista_iter_per_s": round(iters / t_batch, 2),
         "batched_eager_fista_iter_per_s": round(iters / t_eager, 2),
@@ -206,7 +208,7 @@ def batch_leg(P, torch, iters: int) -> dict:
         "batched_pairs_per_s": round(1.0 / tp_batch, 2),
         "per_scan_pairs_per_s": round(1.0 / tp_scan, 2),
         "pairs_speedup": round(tp_scan / tp_batch, 3),
-        "note": "an iteration or pair covers all 64 scans; whole calls are timed (set-up and output included)",
+        "note": f"an iteration or pair covers all {nscans} scans; whole calls are timed (set-up and output included)",
     }
 
 
@@ -380,6 +382,9 @@ def main() -> int:
     iter_bytes = sum(nbytes[k] for k in ("nufft_fwd", "nufft_adj", "fista_update"))
 
     batched = None if args.no_batch else batch_leg(P, torch, args.batch_iters)
+    # many small scans, where one launch per pass per scan is dominated by launch latency
+    batched_small = None if args.no_batch else batch_leg(
+        P, torch, args.batch_iters, nscans=256, nx_choices=(64, 128, 192, 256), nk_choices=(256, 512))
     volume = None if args.no_volume else volume_leg(P, torch, args.volume_iters)
 
     cpu = None
@@ -412,6 +417,7 @@ def main() -> int:
                           "frac": round(iter_bytes * args.steps / wall / 1e9 / HBM_PEAK_GBS, 4)},
         "passes": per_pass,
         "batched": batched,
+        "batched_small_scans": batched_small,
         "volume": volume,
         "cpu_baseline": cpu,
         "gpu": torch.cuda.get_device_name(0),
