@@ -225,7 +225,7 @@ int build_maps(isam_batch_t b) {
     }
     for (Group& g : b->nu) {
         add(g, 0, [](const isam_plan_s* p) { return isam::nufft_fwd_blocks(p); });
-        add(g, 1, [](const isam_plan_s* p) { return p->ncol; });
+        add(g, 1, [](const isam_plan_s* p) { return isam::nufft_adj_blocks(p); });
     }
     if ((int)h.size() > b->maps_cap) {
         if (b->maps) (void)hipFree(b->maps);
@@ -268,7 +268,7 @@ void fill_static_records(isam_batch_t b) {
         for (int k = 0; k < NK_COUNT; ++k) {
             NuScan& r = b->nurec[k].host[i];
             r.a = p->nufft_args();
-            r.nblk = (k == NK_FWD_OP || k == NK_FWD_FISTA) ? rb : p->ncol;
+            r.nblk = (k == NK_FWD_OP || k == NK_FWD_FISTA) ? rb : isam::nufft_adj_blocks(p);
         }
         NuScan* r = b->nurec[NK_FWD_OP].host.data() + i;
         r->in = p->etahat, r->in2 = nullptr, r->out = p->zh, r->partials = nullptr;

@@ -8,12 +8,15 @@
 ISAM_DEV float2 c2(float x, float y) { return make_float2(x, y); }
 ISAM_DEV float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 ISAM_DEV float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+// Products are spelled out as one multiply and one fused multiply-add, so the rounding does
+// not depend on which product the compiler would otherwise contract: every kernel that
+// inlines these (a scan's own launch and a batch launch) rounds alike.
 ISAM_DEV float2 cmul(float2 a, float2 b) {
-    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+    return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
 }
 // a * conj(b)
 ISAM_DEV float2 cmulc(float2 a, float2 b) {
-    return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+    return make_float2(fmaf(a.x, b.x, a.y * b.y), fmaf(a.y, b.x, -(a.x * b.y)));
 }
 ISAM_DEV float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
 ISAM_DEV float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
@@ -33,7 +36,7 @@ ISAM_DEV float2 cfmac(float2 a, float2 b, float2 acc) {
     acc.y = fmaf(-a.y, b.x, acc.y);
     return acc;
 }
-ISAM_DEV float cabs2(float2 a) { return a.x * a.x + a.y * a.y; }
+ISAM_DEV float cabs2(float2 a) { return fmaf(a.x, a.x, a.y * a.y); }
 
 // 64-wide wavefront sum by butterfly shuffles.
 ISAM_DEV float wave_sum(float v) {

@@ -106,7 +106,7 @@ ISAM_DEV float2 rot_const(float2 x) {
     else if constexpr (e == 12) return SIGN > 0 ? c2(x.y, -x.x) : c2(-x.y, x.x);
     else {
         const float c = kCos16[e], s = SIGN * kSin16[e];
-        return c2(x.x * c - x.y * s, x.x * s + x.y * c);
+        return c2(fmaf(x.x, c, -(x.y * s)), fmaf(x.x, s, x.y * c));
     }
 }
 

@@ -46,6 +46,7 @@ struct LatCfg {
     using Fwd = LdsFft<N, C, T, -1, C, L>;
     using Inv = LdsFft<N, C, T, +1, C, L>;
     static_assert(Fwd::EPT == Inv::EPT, "layouts");
+    static_assert(LDS <= 160 * 1024, "lateral tile exceeds the LDS of one CU");
 };
 
 // IB / OB: input / output in the column-blocked layout (else row-major [nx][nk]).
@@ -229,7 +230,7 @@ __global__ __launch_bounds__((LatCfg<N, C>::T)) void k_lat_r2c_batch(const LatSc
 // The hardware square root and reciprocal (about 1 ulp) replace the correctly rounded
 // library forms, whose range scaling and division fix-ups cost more than the transform.
 ISAM_DEV float2 soft_threshold(float2 u, float theta) {
-    const float mag = __builtin_amdgcn_sqrtf(u.x * u.x + u.y * u.y);
+    const float mag = __builtin_amdgcn_sqrtf(fmaf(u.x, u.x, u.y * u.y));
     const float sh = fmaxf(mag - theta, 0.f);
     const float f = theta > 0.f ? sh * __builtin_amdgcn_rcpf(sh + theta) : 1.f;
     return cscale(u, f);

@@ -41,9 +41,11 @@ struct NuCfg {
     static constexpr int BUF = lds_size(K) > K + 8 ? lds_size(K) : K + 8;
     // forward: two columns in parallel (two halves of the block), shared weight table
     static constexpr size_t LDS_FWD = (size_t)(2 * BUF + kWtabEntries) * sizeof(float2);
+    static_assert(LDS_FWD <= 160 * 1024, "forward tile exceeds the LDS of one CU");
 };
 
-// Adjoint: one column per block, radix-8 passes so that K/8 threads share the column.
+// Adjoint: one lateral pair per block, T threads per column (radix-8 passes, so K/8 threads
+// share a column).
 // Samples are processed in chunks of CS; a chunk's cells fit SLOTC slots-triples.
 template <int K>
 struct NuAdjCfg {
@@ -56,13 +58,20 @@ struct NuAdjCfg {
     static constexpr int CS = T < NK / 4 ? T : NK / 4;            // samples per chunk
     static constexpr int NCH = NK / CS;                             // chunks
     static constexpr int SLOTC = 2 * CS + CS / 8 + 16;             // cells of one chunk
-    using Adj = LdsFft<K, 1, T, -1, 1, L, 6>;       // sparser padding: the tile fits 4 workgroups per CU
-    static constexpr size_t YBUF = (size_t)Adj::SIZE * sizeof(float2);
-    static constexpr size_t SLOTS = (size_t)3 * SLOTC * sizeof(float2);
+    using Adj = LdsFft<K, 1, T, -1, 1, L, 6>;       // sparser padding: a smaller tile
+    // per-half strides (float2) of the FFT tiles and of the slot arrays, 16-byte aligned
+    static constexpr int TS = (Adj::SIZE + 1) & ~1;
+    static constexpr int SLS = (3 * SLOTC + 1) & ~1;
     // Y' accumulates in registers (each thread owns the cells its FFT butterflies start from),
-    // so the slot arrays and the FFT tile share one LDS region
-    static constexpr size_t LDS = (size_t)kWtabEntries * sizeof(float2) + (YBUF > SLOTS ? YBUF : SLOTS);
+    // so the two halves' slot arrays and FFT tiles share one LDS region
+    static constexpr size_t LDS =
+        (size_t)(kWtabEntries + (2 * TS > 2 * SLS ? 2 * TS : 2 * SLS)) * sizeof(float2);
     static_assert(SLOTC < K, "a chunk's cells map to distinct oversampled cells");
+    static_assert(LDS <= 160 * 1024, "adjoint tile exceeds the LDS of one CU");
+    // waves per SIMD that the LDS admits (at most 8): the register budget asked of the compiler
+    static constexpr int BPC = (int)((160 * 1024) / LDS);
+    static constexpr int WPE_LDS = BPC * (2 * T / 64) / 4;
+    static constexpr int WPE = WPE_LDS > 8 ? 8 : (WPE_LDS < 1 ? 1 : WPE_LDS);
 };
 
 // Stolt grid position of sample n of a column with q^2 = q2 (FP64).  Returns false on an
@@ -375,8 +384,25 @@ __global__ __launch_bounds__(2 * NuCfg<K>::T) void k_nufft_calgrad(const float2*
     block_sum_store<2 * Cf::T, 3>(acc, reinterpret_cast<float*>(smem), partials + b * kRedSlots);
 }
 
-// Transposed NUFFT of one column per block.  Column l reads the half-spectrum row
-// min(l, nx - l) of the real residual's lateral transform (conjugated above nx/2).
+// Clears the chunk's slot arrays ([3][SLOTC] float2) with 16-byte stores.
+template <typename Cf>
+ISAM_DEV void zero_slots(float2* SL, int tid) {
+    constexpr int N2 = 3 * Cf::SLOTC, N4 = N2 / 2;
+    float4* s4 = reinterpret_cast<float4*>(SL);
+#pragma unroll
+    for (int r = 0; r < (N4 + Cf::T - 1) / Cf::T; ++r) {
+        const int i = tid + r * Cf::T;
+        if (i < N4) s4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    if (N2 & 1) {
+        if (tid == 0) SL[N2 - 1] = c2(0.f, 0.f);
+    }
+}
+
+// Transposed NUFFT of the columns of one lateral pair per block (the pairs of the forward
+// kernel: partners l and nx - l, or one or two self-paired columns).  A column reads its own
+// half-spectrum row of the real residual's lateral transform, or, above nx/2, its partner's
+// row conjugated.
 //
 // The transposed interpolation Y'[g] = sum over (n, j) with g0_n + j = g of
 // conj(u_j(tau_n)) V_n is formed chunk by chunk without atomics: within a chunk every
@@ -385,37 +411,45 @@ __global__ __launch_bounds__(2 * NuCfg<K>::T) void k_nufft_calgrad(const float2*
 // never share a slot: each slot has one writer.  Each cell then sums its three slots (in
 // slot order) into Y'[cell mod K]; chunks follow one another, so every sum is formed in a
 // fixed order and the result is bitwise repeatable.
+//
+// Block = two halves of T threads; half h owns column h of the pair (its slots, its Y' in
+// registers, its inverse FFT).  Partners share q^2, hence their Stolt points and weights:
+// both halves take the same samples and half h evaluates taps 3h .. 3h + 2 for both
+// columns.  Self-paired columns have their own q^2; each half then runs its own column
+// with all J taps.
 template <int K>
 ISAM_DEV void nufft_adj_body(const float2* __restrict__ rh, float2* __restrict__ ghat, const NufftArgs& a,
                              int bidx, int nblk) {
     using Cf = NuAdjCfg<K>;
     using F = typename Cf::Adj;
     constexpr int T = Cf::T;
+    static_assert(kJ == 6, "taps split 3 + 3 between the halves");
     if (a.stop && *a.stop) return;                     // solver already stopped (uniform)
     extern __shared__ float2 smem[];
-    __shared__ int s_red[T / 64];
+    __shared__ int s_red[2][T / 64];
+    const int half = threadIdx.x / T, tid = threadIdx.x % T;
     float2* wt = smem;
-    float2* Y = smem + kWtabEntries;                                  // the FFT tile
-    float2* SL = Y;                                                   // [3][SLOTC] (same region)
-    const int tid = threadIdx.x;
-    // Column order 0, 1, nx-1, 2, nx-2, ..., nx/2 placed XCD by XCD: both columns of a
-    // half-spectrum row and the neighbouring rows (which share cache lines in the blocked
-    // layout) are read through one XCD's L2.
-    const int pos = xcd_tile(bidx, nblk);
-    const int2 ce = a.adjcols[pos];
-    const int col = ce.x;
-    const bool conj_in = ce.y < 0;
-    const int row = conj_in ? -1 - ce.y : ce.y;
-    for (int i = tid; i < kWtabEntries; i += T) wt[i] = a.wtab[i];
-    const double q2 = a.q2[col];
-    const float Bl = a.Bl[col];
-    // residual spectrum and modulation of the thread's samples, fetched up front
-    float2 xr[Cf::NCH], en[Cf::NCH];
+    float2* Y = smem + kWtabEntries + half * Cf::TS;                  // this half's FFT tile
+    float2* SL0 = smem + kWtabEntries;                                // [2][SLS]: slots (same region)
+    float2* SL = SL0 + half * Cf::SLS;
+    // neighbouring pairs (which share cache lines of the blocked layout) on one XCD
+    const FwdPair pr = a.pairs[xcd_tile(bidx, nblk)];
+    const bool pair = pr.mode == 0;
+    const bool live = half == 0 || pr.mode != 2;       // mode 2: a single self-paired column
+    const int col = half == 0 ? pr.a : pr.b;
+    for (int i = threadIdx.x; i < kWtabEntries; i += 2 * T) wt[i] = a.wtab[i];
+    const int scol = pair ? pr.a : col;                // column whose Stolt points this half takes
+    const double q2 = a.q2[scol];
+    const float Bl = a.Bl[scol];
+    // residual spectrum (of pr.a for a pair, else of the half's own column) of the thread's
+    // samples, fetched up front.  The partner of a pair reads its own row
+    // when it is stored (a volume's lx = 0 or nx/2 plane), else the conjugate of pr.a's.
+    const int row0 = pair || !live || half == 0 ? pr.ha : pr.hb;
+    float2 xr0[Cf::NCH];
 #pragma unroll
     for (int ch = 0; ch < Cf::NCH; ++ch) {
         const int n = min(ch * Cf::CS + tid, a.nk - 1);
-        xr[ch] = rh[blk(row, n, a.nhalf)];
-        en[ch] = a.En[n];
+        xr0[ch] = live ? rh[blk(row0, n, a.nhalf)] : c2(0.f, 0.f);
     }
     // Y'[x] for the cells x = b + j K / RO this thread starts the inverse FFT from
     float2 v[F::EPT];
@@ -423,41 +457,60 @@ ISAM_DEV void nufft_adj_body(const float2* __restrict__ rh, float2* __restrict__
     for (int e = 0; e < F::EPT; ++e) v[e] = c2(0.f, 0.f);
     for (int ch = 0; ch < Cf::NCH; ++ch) {
         const int n = ch * Cf::CS + tid;
-        const bool mine = tid < Cf::CS;
+        const bool mine = live && tid < Cf::CS;
         double t;
         int fl = 0;
         float tau = 0.f;
         const bool prop = mine && stolt_point(a, q2, n, t, fl, tau);
-        float2 vn = c2(0.f, 0.f);
+        float2 v0 = c2(0.f, 0.f), v1 = c2(0.f, 0.f);
         if (prop) {
-            const float2 x = conj_in ? cconj(xr[ch]) : xr[ch];
-            vn = cmulc(x, modulation(a, en[ch], Bl, t));
+            const float2 m = modulation(a, a.En[n], Bl, t);
+            v0 = cmulc(xr0[ch], m);
+            if (pair) v1 = cmulc(pr.hb >= 0 ? rh[blk(pr.hb, n, a.nhalf)] : cconj(xr0[ch]), m);
         }
-        // chunk base: smallest g0 among its propagating samples (g0 grows with n)
-        int g0 = prop ? fl - kJ / 2 : 0x7fffffff;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) g0 = min(g0, __shfl_xor(g0, off, 64));
-        if ((tid & 63) == 0) s_red[tid >> 6] = g0;
-        for (int i = tid; i < 3 * Cf::SLOTC; i += T) SL[i] = c2(0.f, 0.f);
+        // chunk base: smallest g0 among the half's propagating samples.  t grows with n and
+        // the evanescent samples come first, so within a wave it is the g0 of the first
+        // propagating lane (read with every lane active, so that lane's value is current).
+        const int g0v = fl - kJ / 2;
+        const unsigned long long pm = __ballot(prop);
+        const int g0w = pm ? __builtin_amdgcn_readlane(g0v, (int)__builtin_ctzll(pm)) : 0x7fffffff;
+        if ((tid & 63) == 0) s_red[half][tid >> 6] = g0w;
+        zero_slots<Cf>(SL, tid);
         __syncthreads();
-        int cbase = s_red[0];
+        int cbase = s_red[half][0];
 #pragma unroll
-        for (int w = 1; w < T / 64; ++w) cbase = min(cbase, s_red[w]);
+        for (int w = 1; w < T / 64; ++w) cbase = min(cbase, s_red[half][w]);
         const bool any = cbase != 0x7fffffff;
         if (prop) {
             // cell g0 + 1 + j (relative to cbase + 1), slot j / 2
-            float2* dst = SL + (fl - kJ / 2 - cbase);
+            const int off = fl - kJ / 2 - cbase;
             const float tp = tau * kPieces;
             const int p = min((int)tp, kPieces - 1);
             const float xl = tp - (float)p;
             const float4* rowp = reinterpret_cast<const float4*>(wt + p * kWtabPiece);
+            if (pair) {
+                float2* d0 = SL0 + off;
+                float2* d1 = SL0 + Cf::SLS + off;
 #pragma unroll
-            for (int jj = 0; jj < kJ; ++jj) {
-                const float4 ca = rowp[2 * jj], cb = rowp[2 * jj + 1];
-                float2 w;
-                w.x = fmaf(fmaf(fmaf(cb.z, xl, cb.x), xl, ca.z), xl, ca.x);
-                w.y = fmaf(fmaf(fmaf(cb.w, xl, cb.y), xl, ca.w), xl, ca.y);
-                dst[(jj >> 1) * Cf::SLOTC + jj] = cfmac(w, vn, c2(0.f, 0.f));
+                for (int k3 = 0; k3 < 3; ++k3) {
+                    const int jj = 3 * half + k3;
+                    const float4 ca = rowp[2 * jj], cb = rowp[2 * jj + 1];
+                    float2 w;
+                    w.x = fmaf(fmaf(fmaf(cb.z, xl, cb.x), xl, ca.z), xl, ca.x);
+                    w.y = fmaf(fmaf(fmaf(cb.w, xl, cb.y), xl, ca.w), xl, ca.y);
+                    d0[(jj >> 1) * Cf::SLOTC + jj] = cfmac(w, v0, c2(0.f, 0.f));
+                    d1[(jj >> 1) * Cf::SLOTC + jj] = cfmac(w, v1, c2(0.f, 0.f));
+                }
+            } else {
+                float2* d0 = SL + off;
+#pragma unroll
+                for (int jj = 0; jj < kJ; ++jj) {
+                    const float4 ca = rowp[2 * jj], cb = rowp[2 * jj + 1];
+                    float2 w;
+                    w.x = fmaf(fmaf(fmaf(cb.z, xl, cb.x), xl, ca.z), xl, ca.x);
+                    w.y = fmaf(fmaf(fmaf(cb.w, xl, cb.y), xl, ca.w), xl, ca.y);
+                    d0[(jj >> 1) * Cf::SLOTC + jj] = cfmac(w, v0, c2(0.f, 0.f));
+                }
             }
         }
         __syncthreads();
@@ -481,6 +534,7 @@ ISAM_DEV void nufft_adj_body(const float2* __restrict__ rh, float2* __restrict__
         __syncthreads();
     }
     F::run(v, Y, a.tw8, tid);         // opens with a barrier: the last reads of the slots are done
+    if (!live) return;
 #pragma unroll
     for (int i = 0; i < F::BPTO; ++i) {
         int cc, b;
@@ -496,13 +550,13 @@ ISAM_DEV void nufft_adj_body(const float2* __restrict__ rh, float2* __restrict__
 }
 
 template <int K>
-__global__ __launch_bounds__(NuAdjCfg<K>::T) void k_nufft_adj(const float2* __restrict__ rh,
+__global__ __launch_bounds__(2 * NuAdjCfg<K>::T, NuAdjCfg<K>::WPE) void k_nufft_adj(const float2* __restrict__ rh,
                                                               float2* __restrict__ ghat, NufftArgs a) {
     nufft_adj_body<K>(rh, ghat, a, blockIdx.x, gridDim.x);
 }
 
 template <int K>
-__global__ __launch_bounds__(NuAdjCfg<K>::T) void k_nufft_adj_batch(const NuScan* __restrict__ scans,
+__global__ __launch_bounds__(2 * NuAdjCfg<K>::T, NuAdjCfg<K>::WPE) void k_nufft_adj_batch(const NuScan* __restrict__ scans,
                                                                     const int2* __restrict__ map) {
     const int2 m = map[blockIdx.x];
     if (m.x < 0) return;                               // padding entry (uniform)
@@ -544,7 +598,7 @@ hipError_t launch_adj(const isam_plan_s* p, const float2* rh, float2* ghat, hipS
     set_lds(k_nufft_adj<K>, Cf::LDS);
     NufftArgs a = p->nufft_args();
     a.stop = stop;
-    ISAM_LAUNCH(k_nufft_adj<K>, dim3(p->ncol), dim3(Cf::T), Cf::LDS, s, rh, ghat, a);
+    ISAM_LAUNCH(k_nufft_adj<K>, dim3(nufft_adj_blocks(p)), dim3(2 * Cf::T), Cf::LDS, s, rh, ghat, a);
     return hipGetLastError();
 }
 
@@ -605,7 +659,7 @@ hipError_t nufft_adj_batch(int K_, const NuScan* recs, const int2* map, int nblk
     ISAM_K_SWITCH(K_, {
         using Cf = NuAdjCfg<K>;
         set_lds(k_nufft_adj_batch<K>, Cf::LDS);
-        hipLaunchKernelGGL(k_nufft_adj_batch<K>, dim3(nblk), dim3(Cf::T), Cf::LDS, s, recs, map);
+        hipLaunchKernelGGL(k_nufft_adj_batch<K>, dim3(nblk), dim3(2 * Cf::T), Cf::LDS, s, recs, map);
         return hipGetLastError();
     });
 }
@@ -616,6 +670,7 @@ hipError_t nufft_adj_batch(int K_, const NuScan* recs, const int2* map, int nblk
 // chunk of samples, [g0_first + 1, g0_last + J], fit the chunk's slot array.  A margin of
 // a few cells covers FP64 rounding differences between host and device at floor boundaries.
 int nufft_fwd_blocks(const isam_plan_s* p) { return p->npairs; }
+int nufft_adj_blocks(const isam_plan_s* p) { return p->npairs; }
 
 int nufft_span_ok(const isam_plan_s* p) {
     int cs = 64;

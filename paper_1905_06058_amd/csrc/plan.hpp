@@ -58,8 +58,7 @@ struct NufftArgs {
     const int* stop;        // solver stop flag (non-zero: return at once), or null
     int ncol;               // lateral-frequency columns (nx for a B-scan, nx * ny for a volume)
     int nhalf;              // columns of the Hermitian half arrays (nx/2 + 1, times ny)
-    const FwdPair* pairs;   // forward NUFFT: column pair of each workgroup
-    const int2* adjcols;    // adjoint NUFFT: (column, half row; -1 - row if conjugated) per workgroup
+    const FwdPair* pairs;   // NUFFT (forward and adjoint): column pair of each workgroup
 };
 
 
@@ -121,7 +120,7 @@ struct isam_plan_s {
     int nx, nk, K, nh;
     int ny = 1;                   // A-scan rows of a volume (1 for a B-scan)
     int ncol = 0, nhalf = 0;      // lateral-frequency columns: nx * ny, (nx/2 + 1) * ny
-    int npairs = 0;               // forward NUFFT workgroups
+    int npairs = 0;               // NUFFT workgroups
     double kc, band, dk, dz, cT, beta, mf;
     int mi;
     double mr;
@@ -139,8 +138,7 @@ struct isam_plan_s {
     float2* twK8 = nullptr;
     float2* twX[5] = {};          // staged lateral twiddles for radix caps 2^2, 2^3, 2^4 (index = log2 cap)
     float2* twY[5] = {};          // the same for the y transform of a volume
-    isam::FwdPair* pairs = nullptr;   // [npairs] forward NUFFT column pairs
-    int2* adjcols = nullptr;          // [ncol] adjoint NUFFT columns
+    isam::FwdPair* pairs = nullptr;   // [npairs] NUFFT column pairs
     double* wscratch = nullptr;   // FP64 scratch of the weight-table build
 
     // workspace (device)
@@ -212,6 +210,7 @@ int fista_finish(isam_plan_t p, double L, int add_residual, float2* out, hipStre
 // powers of two from 192 up to 1792).
 bool lat_supported(int nx);
 int nufft_fwd_blocks(const isam_plan_s* p);
+int nufft_adj_blocks(const isam_plan_s* p);
 hipError_t nufft_adj(const isam_plan_s* p, const float2* rh, float2* ghat, hipStream_t s,
                      const int* stop = nullptr);
 hipError_t nufft_calgrad(const isam_plan_s* p, const float2* etahat, const float2* ghalf, float* partials,

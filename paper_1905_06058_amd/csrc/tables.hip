@@ -260,10 +260,9 @@ void cubic_nodes(double nodes[4], double vinv[16]) {
 
 // Lateral-frequency columns (Eq. 2 over one or two lateral axes): column col = lx * ny + ly;
 // the Hermitian half keeps lx <= nx/2 at the same index.  The partner of (lx, ly) is
-// (-lx mod nx, -ly mod ny).  Forward NUFFT workgroups: first the self-paired columns, two
-// per workgroup, then one partner pair per workgroup; adjoint workgroups: each stored column
-// followed by its unstored partner (for a B-scan the order 0, 1, nx-1, 2, nx-2, ..., nx/2).
-void build_columns(const isam_plan_s* p, std::vector<isam::FwdPair>& pairs, std::vector<int2>& cols) {
+// (-lx mod nx, -ly mod ny).  NUFFT workgroups (forward and adjoint): first the self-paired
+// columns, two per workgroup, then one partner pair per workgroup.
+void build_columns(const isam_plan_s* p, std::vector<isam::FwdPair>& pairs) {
     const int nx = p->nx, ny = p->ny, nh = p->nhalf;
     auto partner = [&](int c) { return ((nx - c / ny) % nx) * ny + (ny - c % ny) % ny; };
     std::vector<int> self;
@@ -283,11 +282,6 @@ void build_columns(const isam_plan_s* p, std::vector<isam::FwdPair>& pairs, std:
         } else {
             pairs.push_back({c, q, c, -1, 0});
         }
-    }
-    for (int c = 0; c < nh; ++c) {
-        cols.push_back(make_int2(c, c));
-        const int q = partner(c);
-        if (q >= nh) cols.push_back(make_int2(q, -1 - c));
     }
 }
 
@@ -432,7 +426,7 @@ int dalloc(T** ptr, size_t n) {
 
 void release(isam_plan_s* p) {
     void* ptrs[] = {p->q2, p->Bl, p->En, p->sm, p->wtab, p->twK, p->twK8, p->twX[2], p->twX[3], p->twX[4],
-                    p->twY[2], p->twY[3], p->twY[4], p->pairs, p->adjcols, p->wscratch,
+                    p->twY[2], p->twY[3], p->twY[4], p->pairs, p->wscratch,
                     p->etahat, p->zh, p->rh, p->ghat, p->fista_hat, p->yhat, p->vec, p->sbuf, p->wbuf, p->zblk,
                     p->xs, p->xsh, p->red.partials, p->red.sums};
     for (void* q : ptrs)
@@ -471,7 +465,6 @@ isam::NufftArgs isam_plan_s::nufft_args() const {
     a.ncol = ncol;
     a.nhalf = nhalf;
     a.pairs = pairs;
-    a.adjcols = adjcols;
     return a;
 }
 
@@ -500,18 +493,14 @@ extern "C" int isam_plan(const isam_geometry* g, void* stream, isam_plan_t* out)
     p->red.maxBlocks = p->ncol + 2 * p->nk * p->ny + 2048;
     const int nsums = kPieces * 4 * kJ + (2 * kJ - 1);
     std::vector<isam::FwdPair> hp;
-    std::vector<int2> hc;
-    build_columns(p, hp, hc);
+    build_columns(p, hp);
     p->npairs = (int)hp.size();
     rc = ISAM_OK;
     rc = rc ? rc : dalloc(&p->q2, p->ncol);
     rc = rc ? rc : dalloc(&p->Bl, p->ncol);
     rc = rc ? rc : dalloc(&p->pairs, hp.size());
-    rc = rc ? rc : dalloc(&p->adjcols, hc.size());
-    if (rc == ISAM_OK && (hipMemcpy(p->pairs, hp.data(), hp.size() * sizeof(isam::FwdPair), hipMemcpyHostToDevice) !=
-                              hipSuccess ||
-                          hipMemcpy(p->adjcols, hc.data(), hc.size() * sizeof(int2), hipMemcpyHostToDevice) !=
-                              hipSuccess))
+    if (rc == ISAM_OK &&
+        hipMemcpy(p->pairs, hp.data(), hp.size() * sizeof(isam::FwdPair), hipMemcpyHostToDevice) != hipSuccess)
         rc = ISAM_EHIP;
     if (p->ny > 1) {
         for (int L = 2; L <= 4; ++L) rc = rc ? rc : dalloc(&p->twY[L], fft_stage_len(p->ny, L));

@@ -42,7 +42,8 @@ def rand_case(nx, nk, seed, **kw):
     return o, eta, r
 
 
-SIZES = [(1, 64), (2, 32), (4, 16), (8, 64), (16, 128), (32, 256), (64, 512), (128, 64), (256, 32)]
+SIZES = [(1, 64), (2, 32), (4, 16), (8, 64), (16, 128), (32, 256), (64, 512), (128, 64), (256, 32), (4, 2048),
+         (8, 4096)]
 
 
 @pytest.mark.parametrize("nx,nk", SIZES)
