@@ -79,11 +79,12 @@ def pass_bytes(nx: int, nk: int, weighted: bool) -> dict:
 
 def pass_flops(nx: int, nk: int, J: int = 6) -> dict:
     """Algorithmic FP32 flops per launch: 5 N log2 N per complex FFT of length N, and per
-    Stolt sample J weights (cubic complex Horner, 12 flops), J complex multiply-adds (8)
-    and the modulation product (6)."""
+    Stolt sample of a column J complex multiply-adds (8 flops) and the modulation product
+    (6), plus the J weights (cubic complex Horner, 12 flops each) once per partner pair l,
+    nx - l, which share q^2 and hence the weights: 6 J per column sample."""
     K = 2 * nk
     fft_col = 5 * K * math.log2(K)
-    per_sample = 12 * J + 8 * J + 6
+    per_sample = 6 * J + 8 * J + 6
     lat = 5 * nx * math.log2(max(nx, 2)) * nk
     return {
         "nufft_fwd": nx * (fft_col + per_sample * nk),
