@@ -72,6 +72,21 @@ def test_mixed_radix_lateral_lengths(P, nx, nk):
     assert rel(a, O.adjoint_nufft(g, r)) < TOL_OP
 
 
+# the widest built lateral lengths, with 4-lane tiles at 2048 (one or two tiles per pass)
+SIZES_WIDE = [(512, 32), (1024, 16), (1280, 16), (1792, 16), (2048, 16)]
+
+
+@pytest.mark.parametrize("nx,nk", SIZES_WIDE)
+def test_wide_lateral_lengths(P, nx, nk):
+    o, eta, r = rand_case(nx, nk, seed=3 * nx + nk)
+    g = O.Geometry.of(o)
+    with make_plan(P, o) as plan:
+        s = to_host(plan.forward(to_dev(eta)))
+        a = to_host(plan.adjoint(to_dev(r)))
+    assert rel(s, O.forward_nufft(g, eta)) < TOL_OP
+    assert rel(a, O.adjoint_nufft(g, r)) < TOL_OP
+
+
 @pytest.mark.parametrize("focus_rows", [0, -37, 13.25, 64.5])
 def test_focus_and_dispersion_variants(P, focus_rows):
     """Integer, negative and fractional focal rows (the fractional part takes the per-sample phase)."""
