@@ -37,7 +37,7 @@ def parse():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200, help="timed FISTA iterations")
-    ap.add_argument("--warmup", type=int, default=20, help="untimed FISTA iterations before timing")
+    ap.add_argument("--warmup", type=int, default=200, help="untimed FISTA iterations before timing")
     ap.add_argument("--pairs", type=int, default=200, help="timed A.A^H pairs")
     ap.add_argument("--workload", default="bscan")
     ap.add_argument("--no-cpu-baseline", action="store_true")
