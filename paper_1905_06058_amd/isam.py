@@ -53,6 +53,12 @@ class Geometry(ctypes.Structure):
         ("J", ctypes.c_int32), ("osf", ctypes.c_int32), ("kb_beta", ctypes.c_double),
     ]
 
+    def __init__(self, nx=0, ny=1, nk=0, dx=0.0, dy=0.0, lambda_c=0.0, dlambda=0.0, waist=0.0,
+                 z_focus=0.0, a2=0.0, a3=0.0, J=6, osf=2, kb_beta=0.0):
+        """B-scan by default (ny = 1); J = 6, 2x oversampling and the default Kaiser-Bessel
+        scaling (kb_beta = 0) are the values the library implements."""
+        super().__init__(nx, ny, nk, dx, dy, lambda_c, dlambda, waist, z_focus, a2, a3, J, osf, kb_beta)
+
     @classmethod
     def of(cls, o, **overrides) -> "Geometry":
         """From any record carrying nx, nk, dx, lambda_c, dlambda, waist, z_focus, a2, a3."""
