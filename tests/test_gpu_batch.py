@@ -71,6 +71,28 @@ def test_batch_operator_matches_scan_plans_and_oracle(P):
         assert rel(to_host(b.scan(a, i)), O.adjoint_nufft(g, rs[i])) < 1e-5
 
 
+# scans at the depth lengths of the uneven-batch workload (K = 2048 and 4096 NUFFT kernels)
+SCANS_DEEP = [(8, 2048, 30, 6, 300.5), (64, 1024, 20, -4, -100), (32, 2048, 12, 2, 512), (192, 1024, 40, 8, 7)]
+
+
+def test_batch_at_full_depth_lengths_matches_scan_plans_and_oracle(P):
+    import torch
+    opts = optics_list(SCANS_DEEP)
+    etas, rs = batch_data(opts, 11)
+    with P.Batch([P.Geometry.of(o) for o in opts]) as b:
+        eta = packed(b, etas, torch.complex64)
+        r = packed(b, rs, torch.float32)
+        s = b.forward(eta)
+        a = b.adjoint(r)
+        for i in range(b.n):
+            p = b.plan(i)
+            assert bool((b.scan(s, i) == p.forward(b.scan(eta, i).contiguous())).all()), i
+            assert bool((b.scan(a, i) == p.adjoint(b.scan(r, i).contiguous())).all()), i
+        g = O.Geometry.of(opts[0])                         # 8 x 2048, fractional focal row
+        assert rel(to_host(b.scan(s, 0)), O.forward_nufft(g, etas[0])) < 1e-5
+        assert rel(to_host(b.scan(a, 0)), O.adjoint_nufft(g, rs[0])) < 1e-5
+
+
 def _problem(P, b, opts, seed):
     import torch
     rng = np.random.default_rng(seed)
