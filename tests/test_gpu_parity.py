@@ -208,7 +208,9 @@ def _fista_case(P, name, iters, **kw):
     y = ph.add_noise(op.A(ph.phantom(w)), w.snr_db, w.seed)
     with make_plan(P, w.optics) as plan:
         L = plan.lipschitz(iters=50, seed=0)
-        lam = w.lam_frac * plan.lambda_max(to_dev(y))
+        lam = kw.pop("lam_override", None)
+        if lam is None:
+            lam = w.lam_frac * plan.lambda_max(to_dev(y))
         wts = kw.pop("weights", None)
         res = plan.fista(to_dev(y), lam, iters, L=L, w=None if wts is None else to_dev(wts), **kw)
         z = to_host(res.eta)
@@ -224,6 +226,34 @@ def res_lam(res, ref):
 def test_fista_tiny_fixed_iterations(P):
     z, ref, res = _fista_case(P, "tiny", 100)
     assert res.iters == 100 and res.status == 0
+    assert rel(z, ref.z) < TOL_FISTA
+    assert abs(res.resid2 - ref.resid2[-1]) < 1e-4 * ref.resid2[-1]
+
+
+def test_fista_above_lambda_max_stays_at_zero(P):
+    """Eq. 14 at lambda >= lambda_max = max|A^H y| / w: from eta^1 = 0 every soft threshold
+    returns zero, so the iterate stays exactly zero and the residual is -y."""
+    w = ph.workload("tiny")
+    g = O.Geometry.of(w.optics)
+    y = ph.add_noise(O.Operator(g, "N").A(ph.phantom(w)), w.snr_db, w.seed)
+    with make_plan(P, w.optics) as plan:
+        L = plan.lipschitz(iters=50, seed=0)
+        lam = 1.05 * plan.lambda_max(to_dev(y))
+        res = plan.fista(to_dev(y), lam, 30, L=L)
+        assert res.status == 0
+        assert not bool(res.eta.abs().max() > 0)
+        assert abs(res.resid2 - float((y ** 2).sum())) <= 1e-5 * float((y ** 2).sum())
+        assert res.l1 == 0.0
+
+
+def test_fista_zero_iterations_and_zero_lambda(P):
+    """max_iter = 0 returns the starting point eta^1 = 0; lambda = 0 (plain least squares by
+    FISTA) follows the oracle."""
+    with make_plan(P, ph.workload("tiny").optics) as plan:
+        y = to_dev(np.ones((64, 256)))
+        res = plan.fista(y, 0.1, 0, L=1.01)
+        assert res.status == 0 and not bool(res.eta.abs().max() > 0)
+    z, ref, res = _fista_case(P, "tiny", 40, lam_override=0.0)
     assert rel(z, ref.z) < TOL_FISTA
     assert abs(res.resid2 - ref.resid2[-1]) < 1e-4 * ref.resid2[-1]
 
