@@ -16,9 +16,10 @@
 // C2R lateral pass turns into Re(F^{-1} X) (Eq. 5), or, in the solver, the residual
 // spectrum Z - F(y).
 //
-// Adjoint: the exact transpose, one column per workgroup.  The transposed interpolation
-// is formed without atomics (see k_nufft_adj): t_n increases by at least 2 per sample,
-// so the contributions to a cell can be given fixed, single-writer slots.
+// Adjoint: the exact transpose, one lateral pair per workgroup (partners share their
+// Stolt points and weights).  The transposed interpolation is formed without atomics (see
+// nufft_adj_body): t_n increases by at least 2 per sample, so the contributions to a cell
+// can be given fixed, single-writer slots.
 #include <algorithm>
 
 #include "common.hpp"
