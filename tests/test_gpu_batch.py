@@ -72,7 +72,9 @@ def test_batch_operator_matches_scan_plans_and_oracle(P):
 
 
 # scans at the depth lengths of the uneven-batch workload (K = 2048 and 4096 NUFFT kernels)
-SCANS_DEEP = [(8, 2048, 30, 6, 300.5), (64, 1024, 20, -4, -100), (32, 2048, 12, 2, 512), (192, 1024, 40, 8, 7)]
+# and one at the longest supported depth (K = 8192)
+SCANS_DEEP = [(8, 2048, 30, 6, 300.5), (64, 1024, 20, -4, -100), (32, 2048, 12, 2, 512), (192, 1024, 40, 8, 7),
+              (16, 4096, 25, 3, 1024)]
 
 
 def test_batch_at_full_depth_lengths_matches_scan_plans_and_oracle(P):
