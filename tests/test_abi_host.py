@@ -122,3 +122,41 @@ def test_valid_geometry_without_device_reports_enodev(lib):
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
     assert _plan_rc(lib, _geom()) == -5
+
+
+C_CONSUMER = r"""
+#include <stdio.h>
+#include <string.h>
+#include "isam.h"
+int main(void) {
+    isam_geometry g;
+    isam_plan_t p = 0;
+    memset(&g, 0, sizeof g);                      /* nx = 0: rejected before any device call */
+    if (isam_plan(&g, 0, &p) != ISAM_EINVAL || p != 0) return 1;
+    if (isam_forward(0, 0, 0, 0) != ISAM_EINVAL) return 2;
+    if (isam_strerror(ISAM_OK) == 0 || isam_strerror(ISAM_EINVAL)[0] == 0) return 3;
+    printf("%s\n", isam_strerror(ISAM_EINVAL));
+    return 0;
+}
+"""
+
+
+def test_header_is_plain_c_and_links(lib, tmp_path):
+    """include/isam.h is ISO C99 (no C++ in the signatures); a C program links libisam.so
+    and gets argument errors back without a device."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "consumer.c"
+    src.write_text(C_CONSUMER)
+    exe = tmp_path / "consumer"
+    libdir = os.path.dirname(P.LIB_PATH)
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I",
+                        os.path.join(ROOT, "include"), str(src), "-L", libdir, "-lisam",
+                        "-Wl,-rpath," + libdir, "-o", str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, (r.returncode, r.stdout, r.stderr)
+    assert r.stdout.strip()
