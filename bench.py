@@ -23,7 +23,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E
-# FP32 vector peak without packed-FP32 instructions (this build does not emit them):
+# FP32 vector peak without packed-FP32 instructions (the kernels are compiled without them):
 # 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.
 ALU_PEAK_TFS = 78.6
 METRIC = "A^H·A op pairs/s + FISTA iter/s, 1024×2048 B-scan FP32 vs plain; %HBM peak"
@@ -271,8 +271,8 @@ def volume_leg(P, torch, iters: int) -> dict:
 def main() -> int:
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(independent B-scans shard without communication; see the design notes)", file=sys.stderr)
+        print(f"bench.py: measures one GPU; --gpus {args.gpus} is not supported "
+              "(independent B-scans would shard across GPUs without communication)", file=sys.stderr)
         return 2
     import numpy as np
     import torch

@@ -27,9 +27,9 @@ Two operator modes:
     2x oversampled FFT, J-tap interpolation whose weights solve, per point, the
     least-squares problem that defines the min-max interpolator.
 
-Readings of passages the paper leaves open (sign conventions, normalisations,
-beam filter and focus model, step size) are the ones listed in the design notes;
-each function names the passage it follows.
+Where the paper leaves a passage open (sign conventions, normalisations, beam
+filter and focus model, step size), the function that depends on it states the
+reading it takes; each function names the passage it follows.
 """
 from __future__ import annotations
 
