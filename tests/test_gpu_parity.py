@@ -87,6 +87,23 @@ def test_wide_lateral_lengths(P, nx, nk):
     assert rel(a, O.adjoint_nufft(g, r)) < TOL_OP
 
 
+def test_full_range_ambiguity_without_dispersion(P):
+    """With no dispersion and the focus at zero delay, an object and its conjugate mirror
+    conj(eta[p][-m]) give the same real spectra (Eq. 5, 6): the ambiguity that dispersion
+    encoding removes.  With dispersion they differ at O(1)."""
+    nx, nk = 64, 256
+    rng = np.random.default_rng(21)
+    eta = ph.complex_gaussian(rng, (nx, nk))
+    eta[:, 0] = 0.0                                   # row m = -nz/2 has no mirror partner
+    mir = np.zeros_like(eta)
+    mir[:, 1:] = np.conj(eta[:, :0:-1])
+    o0 = ph.custom_optics(nx, nk, edge_phase2=0.0, edge_phase3=0.0, focus_rows=0)
+    o1 = ph.custom_optics(nx, nk, edge_phase2=20 * math.pi, edge_phase3=0.0, focus_rows=0)
+    with make_plan(P, o0) as p0, make_plan(P, o1) as p1:
+        assert rel(to_host(p0.forward(to_dev(mir))), to_host(p0.forward(to_dev(eta)))) < 1e-5
+        assert rel(to_host(p1.forward(to_dev(mir))), to_host(p1.forward(to_dev(eta)))) > 0.1
+
+
 @pytest.mark.parametrize("focus_rows", [0, -37, 13.25, 64.5])
 def test_focus_and_dispersion_variants(P, focus_rows):
     """Integer, negative and fractional focal rows (the fractional part takes the per-sample phase)."""
