@@ -333,6 +333,17 @@ def main() -> int:
         plan.adjoint(sbuf, out=x)
     torch.cuda.synchronize()
     pair_s = (time.perf_counter() - tp) / max(args.pairs, 1)
+    # the composed normal operator A^H A (isam_normal): the real spectra are not materialised,
+    # since F(Re F^{-1} X) is the Hermitian part of X
+    xn = torch.empty_like(x)
+    for _ in range(20):
+        plan.normal(x, out=xn)
+    torch.cuda.synchronize()
+    tn = time.perf_counter()
+    for _ in range(args.pairs):
+        plan.normal(x, out=xn)
+    torch.cuda.synchronize()
+    normal_s = (time.perf_counter() - tn) / max(args.pairs, 1)
 
     # ---- per-pass kernel durations (HIP events on the launch stream) over a second FISTA run
     plan.timing(True)
@@ -412,6 +423,7 @@ def main() -> int:
         "fista_gpu_ms_per_iter": round(gpu_ms / max(args.steps, 1), 5),
         "pairs_per_s": round(1.0 / pair_s, 2),
         "ms_per_pair": round(1e3 * pair_s, 5),
+        "normal_per_s": round(1.0 / normal_s, 2),
         "roofline": roofline,
         "iteration_hbm": {"algorithmic_bytes": iter_bytes,
                           "GBps": round(iter_bytes * args.steps / wall / 1e9, 1),
