@@ -82,7 +82,11 @@ ISAM_DEV bool stolt_point(const NufftArgs& a, double q2, int n, double& t, int& 
     const double tk = 2.0 * k;
     const double d = fma(tk, tk, -q2);
     if (!(d > 0.0)) return false;
-    t = sqrt(d) * a.cT;
+    // sqrt(d): hardware reciprocal square root refined by one Newton step on the root
+    // (relative error about the square of the estimate's)
+    const double y = __builtin_amdgcn_rsq(d);
+    const double s0 = d * y, h = 0.5 * y;
+    t = fma(h, fma(-s0, s0, d), s0) * a.cT;
     const double f = floor(t);
     fl = (int)f;
     tau = (float)(t - f);
