@@ -151,9 +151,12 @@ int isam_calibration_grad(isam_plan_t p, const void* eta, const float* g, double
  * lambda w_i / L (Eq. 14).  y: device float32 [nx][nk] measured spectra;
  * w: NULL or device float32 [nx][nk] (> 0); eta_out: device complex64
  * [nx][nk], receives z^k (plus (1/L) A^H(y - A z^k) if add_residual).
- * max_iter >= 0 iterations; tol > 0 enables the relative-residual stop of
- * Eq. 15 (one host read per iteration), tol = 0 runs exactly max_iter
- * iterations with no host synchronisation until the end.  L <= 0 runs
+ * max_iter >= 0 iterations (0 returns the start point eta^1 = 0); tol > 0
+ * enables the relative-residual stop of Eq. 15, evaluated on the device after
+ * every update pass (the host reads the stop state every 16 iterations; the
+ * iterations queued after the stopping one return at once, so eta_out is the
+ * stopping iterate); tol = 0 runs exactly max_iter iterations with no host
+ * synchronisation until the end.  L <= 0 runs
  * isam_lipschitz (50 steps, seed 0) first.  info may be NULL.  Synchronises
  * the stream at the end.  Errors: EINVAL, EALIAS, ENONFINITE (info->status). */
 int isam_fista(isam_plan_t p, const float* y, float lambda, const float* w, int max_iter,
