@@ -1,0 +1,101 @@
+"""Planted mistakes in the FP64 oracle (test infrastructure): each entry replaces one oracle
+function with a plausibly wrong version, so that the pins in test_oracle_pins.py can be shown
+to catch it.  Used only by test_oracle_mutations.py, in a separate process per mistake."""
+import math
+
+import numpy as np
+
+import oracle
+import oracle.isam_oracle as OI
+
+
+def _patch(name, fn):
+    setattr(OI, name, fn)
+    setattr(oracle, name, fn)
+
+
+def _wrap(name, make):
+    orig = getattr(OI, name)
+    _patch(name, make(orig))
+
+
+MUTATIONS = {
+    # Eq. 7: dispersion phase with the wrong sign
+    "dispersion_sign": lambda: _wrap("dispersion_phase", lambda f: lambda g: -f(g)),
+    # Eq. 16: beam filter dropped (1 on propagating components)
+    "beam_dropped": lambda: _wrap("beam_filter", lambda f: lambda g: (f(g) > 0).astype(float)),
+    # Eq. 3: kz = sqrt(4 k^2 + q^2) instead of sqrt(4 k^2 - q^2)
+    "kz_sign": lambda: _patch("axial_wavenumber", _kz_plus),
+    # Eq. 2: lateral DFT not unitary
+    "lateral_norm": lambda: _patch("_lateral_fft", lambda x: np.fft.fft(x, axis=0)),
+    # Kaiser-Bessel scaling inverted
+    "kb_inverse": lambda: _wrap("kb_scaling", lambda f: lambda g: 1.0 / f(g)),
+    # min-max weights conjugated
+    "weights_conj": lambda: _wrap("minmax_weights", lambda f: lambda g, tau, chunk=4096: np.conj(f(g, tau, chunk))),
+    # Eq. 14: threshold halved
+    "prox_threshold": lambda: _wrap("soft_threshold", lambda f: lambda u, theta: f(u, np.asarray(theta) / 2)),
+    # Stolt neighbours shifted by one grid cell
+    "stolt_offset": lambda: _wrap("stolt_points", lambda f: lambda g: _shift_g0(f(g))),
+    # focal reference with the wrong sign
+    "focus_sign": lambda: _patch("modulation", _modulation_focus_flipped),
+    # adjoint without the conjugate of the modulation
+    "adjoint_no_conj": lambda: _patch("adjoint_exact", _adjoint_no_conj),
+    # depth pitch 2 pi / band instead of pi / band
+    "depth_pitch": lambda: _wrap("grids", lambda f: lambda g: _double_dz(f(g))),
+    # lambda_max without the weights
+    "lambda_max_unweighted": lambda: _wrap("lambda_max", lambda f: lambda op, y, w=None: f(op, y)),
+    # calibration derivative of the focal reference with the wrong sign of kz
+    "calib_focus_term": lambda: _wrap("calibration_derivatives", lambda f: lambda g: _flip_kz_term(g, f(g))),
+    # volume: the y lateral frequency dropped from q^2
+    "volume_qy_dropped": lambda: _wrap("volume_q2", lambda f: lambda g: _drop_qy(g)),
+}
+
+
+def _flip_kz_term(g, D):
+    G = OI.grids(g)
+    kz, _ = OI.axial_wavenumber(g)
+    return D[0], D[1], 2 * G.k[None, :] + kz
+
+
+def _drop_qy(g):
+    qx = 2 * math.pi * np.fft.fftfreq(g.nx, d=1.0 / g.nx) / (g.nx * g.dx)
+    return np.broadcast_to(qx[None, :] ** 2, (g.ny, g.nx)).copy()
+
+
+def _kz_plus(g):
+    G = OI.grids(g)
+    arg = 4 * G.k[None, :] ** 2 + (G.q ** 2)[:, None]
+    return np.sqrt(arg), np.ones(arg.shape, bool)
+
+
+def _shift_g0(res):
+    t, g0, tau = res
+    return t, g0 + 1, tau
+
+
+def _modulation_focus_flipped(g):
+    G = OI.grids(g)
+    kz, prop = OI.axial_wavenumber(g)
+    c = OI.beam_filter(g) * np.exp(1j * OI.dispersion_phase(g)[None, :]) * \
+        np.exp(-1j * (2 * G.k[None, :] - kz) * g.z_focus)
+    return np.where(prop, c, 0.0)
+
+
+def _adjoint_no_conj(g, r):
+    G = OI.grids(g)
+    R = OI._lateral_fft(np.asarray(r, np.float64).astype(np.complex128))
+    kz, _ = OI.axial_wavenumber(g)
+    Xp = OI.modulation(g) * R
+    eta_hat = np.empty((g.nx, g.nk), np.complex128)
+    for l in range(g.nx):
+        E = np.exp(1j * kz[l][:, None] * G.z[None, :])
+        eta_hat[l] = np.conj(E).T @ Xp[l] / math.sqrt(g.nk)
+    return OI._lateral_ifft(eta_hat)
+
+
+def _double_dz(G):
+    return OI.Grids(G.kc, G.band, G.dk, G.k, 2 * G.dz, G.m, 2 * G.z, G.l, G.q, G.K, G.beta)
+
+
+def apply(name):
+    MUTATIONS[name]()

@@ -408,6 +408,19 @@ def test_fista_zero_solution_above_lambda_max():
     assert np.any(res.z != 0)
 
 
+def test_weighted_lambda_max_is_the_zero_threshold():
+    """Eq. 12 with depth weights: eta = 0 is optimal iff lambda w_i >= |(A^H y)_i| for every
+    i, so weighted FISTA from zero stays at zero just above the weighted lambda_max and moves
+    just below it (the first step is (1/L) A^H y against thresholds lambda w_i / L)."""
+    g, op, y = _tiny_problem()
+    w = ph.depth_weights(g.nx, g.nk)
+    lw = O.lambda_max(op, y, w)
+    assert np.all(O.fista(op, y, lam=lw * 1.0001, L=1.0, iters=3, w=w).z == 0)
+    assert np.any(O.fista(op, y, lam=lw * 0.999, L=1.0, iters=1, w=w).z != 0)
+    # and it is not the unweighted value (the weights rise from 0.5 to 1 with depth)
+    assert abs(lw - O.lambda_max(op, y)) > 1e-3 * lw
+
+
 def test_fista_reaches_kkt_point_and_obeys_rate_bound():
     """Optimality of the limit by the l1 KKT conditions; the O(1/k^2) rate of Beck & Teboulle 2009."""
     g, op, y = _tiny_problem()
