@@ -48,7 +48,24 @@ MUTATIONS = {
     "calib_focus_term": lambda: _wrap("calibration_derivatives", lambda f: lambda g: _flip_kz_term(g, f(g))),
     # volume: the y lateral frequency dropped from q^2
     "volume_qy_dropped": lambda: _wrap("volume_q2", lambda f: lambda g: _drop_qy(g)),
+    # min-max target offset by one grid cell (J/2 - 1 instead of J/2)
+    "minmax_target_offset": lambda: _patch("_targets", _targets_off_by_one),
+    # oversampled depth spectrum with the rows placed one index off
+    "oversampled_placement": lambda: _patch("_oversampled_spectrum", _oversampled_shifted),
 }
+
+
+def _targets_off_by_one(g, tau, m, K):
+    return np.exp(2j * math.pi * np.outer(m, np.asarray(tau) + g.J / 2 - 1) / K)
+
+
+def _oversampled_shifted(g, eta_hat_rows):
+    G = OI.grids(g)
+    s = OI.kb_scaling(g)
+    rows = np.atleast_2d(eta_hat_rows)
+    buf = np.zeros((rows.shape[0], G.K), np.complex128)
+    buf[:, np.mod(G.m + 1, G.K)] = rows * s[None, :]
+    return G.K * np.fft.ifft(buf, axis=1)
 
 
 def _flip_kz_term(g, D):
