@@ -52,7 +52,23 @@ MUTATIONS = {
     "minmax_target_offset": lambda: _patch("_targets", _targets_off_by_one),
     # oversampled depth spectrum with the rows placed one index off
     "oversampled_placement": lambda: _patch("_oversampled_spectrum", _oversampled_shifted),
+    # adjoint NUFFT with the interpolation matrix transposed but not conjugated
+    "adjoint_nufft_no_conj": lambda: _patch("adjoint_nufft", _adjoint_nufft_no_conj),
 }
+
+
+def _adjoint_nufft_no_conj(g, r, columns=None, P=None):
+    G = OI.grids(g)
+    R = OI._lateral_fft(np.asarray(r, np.float64).astype(np.complex128))
+    Xp = np.conj(OI.modulation(g)) * R
+    s = OI.kb_scaling(g)
+    tables = OI.stolt_points(g)
+    eta_hat = np.zeros((g.nx, g.nk), np.complex128)
+    for l in range(g.nx):
+        Pl = P[l] if P is not None else OI._interp_matrix(g, l, None, tables)
+        full = np.fft.fft(Pl.T @ Xp[l])
+        eta_hat[l] = s * full[np.mod(G.m, G.K)] / math.sqrt(g.nk)
+    return OI._lateral_ifft(eta_hat)
 
 
 def _targets_off_by_one(g, tau, m, K):
