@@ -54,7 +54,46 @@ MUTATIONS = {
     "oversampled_placement": lambda: _patch("_oversampled_spectrum", _oversampled_shifted),
     # adjoint NUFFT with the interpolation matrix transposed but not conjugated
     "adjoint_nufft_no_conj": lambda: _patch("adjoint_nufft", _adjoint_nufft_no_conj),
+    # FISTA momentum weight t_k / t_{k+1} instead of (t_k - 1) / t_{k+1}
+    "fista_momentum": lambda: _patch("fista", _fista_wrong_momentum),
 }
+
+
+def _fista_wrong_momentum(op, y, lam, L, iters, w=None, tol=0.0, add_residual=False, eps=1e-12, state=None):
+    y = np.asarray(y, np.float64)
+    step = 1.0 / L
+    w = np.ones(y.shape) if w is None else np.asarray(w, np.float64)
+    theta = lam * w * step
+    if state is None:
+        eta = np.zeros(y.shape, np.complex128)
+        z_prev = np.zeros(y.shape, np.complex128)
+        t = 1.0
+    else:
+        eta, z_prev, t = state[0].copy(), state[1].copy(), state[2]
+    rr_hist, res_hist, l1_hist = [], [], []
+    z = z_prev
+    k = 0
+    for k in range(1, iters + 1):
+        r = op.A(eta) - y
+        gk = step * op.AH(r)
+        z = OI.soft_threshold(eta - gk, theta)
+        d = z - eta
+        rr = np.linalg.norm(d) / (max(np.linalg.norm(gk), np.linalg.norm(d + gk)) + eps)
+        rr_hist.append(rr)
+        res_hist.append(float(np.sum(r * r)))
+        l1_hist.append(float(np.sum(w * np.abs(z))))
+        if tol > 0 and rr < tol:
+            break
+        t_next = (1 + math.sqrt(1 + 4 * t * t)) / 2
+        eta = z + (t / t_next) * (z - z_prev)
+        z_prev = z
+        t = t_next
+    out = z
+    if add_residual:
+        out = z + step * op.AH(y - op.A(z))
+    res = OI.FistaResult(out, k, rr_hist, res_hist, l1_hist)
+    res.state = (eta, z_prev, t)
+    return res
 
 
 def _adjoint_nufft_no_conj(g, r, columns=None, P=None):

@@ -447,6 +447,35 @@ def test_fista_reaches_kkt_point_and_obeys_rate_bound():
     assert short.iters == 1
 
 
+def test_fista_energy_of_beck_teboulle_is_nonincreasing():
+    """Beck & Teboulle 2009, Lemma 4.1: with v_k = F(z^k) - F* and
+    u_k = t_k z^k - (t_k - 1) z^{k-1} - x*, the energy (2/L) t_k^2 v_k + ||u_k||^2 never rises
+    along the iterates of Alg. 1 (t_1 = 1, z^0 = 0).  A wrong momentum weight breaks it."""
+    g, op, y = _tiny_problem()
+    lam = 0.1 * O.lambda_max(op, y)
+    L = 1.0 + 1e-9
+    xs = O.fista(op, y, lam, L, iters=20000).z
+
+    def F(v):
+        r = op.A(v) - y
+        return 0.5 * np.sum(r * r) + lam * np.sum(np.abs(v))
+
+    Fs = F(xs)
+    K = 60
+    t = [1.0]
+    while len(t) < K:
+        t.append((1 + math.sqrt(1 + 4 * t[-1] ** 2)) / 2)
+    zs = [np.zeros_like(xs)] + [O.fista(op, y, lam, L, iters=k).z for k in range(1, K + 1)]
+    E = []
+    for k in range(1, K + 1):
+        tk = t[k - 1]
+        u = tk * zs[k] - (tk - 1) * zs[k - 1] - xs
+        E.append(2 / L * tk ** 2 * (F(zs[k]) - Fs) + np.sum(np.abs(u) ** 2))
+    E = np.asarray(E)
+    assert np.all(np.diff(E) <= 1e-9 * E[0])
+    assert E[-1] < 0.5 * E[0]
+
+
 def test_fista_relative_residual_stop_and_resume():
     g, op, y = _tiny_problem()
     lam = 0.1 * O.lambda_max(op, y)
