@@ -328,4 +328,155 @@ struct LdsFft {
     }
 };
 
+// Two-buffer form of LdsFft (same passes, same register layout, same twiddle table, LDS pad
+// of one slot per 16 elements) for tiles whose LDS does not limit occupancy.  Pass p reads
+// buffer (p - 1) & 1 and writes buffer p & 1, so each pass needs one barrier instead of two;
+// the twiddles of every pass are fetched into registers once (Tw), so no table load waits
+// behind a barrier, and a chained inverse and forward transform share one fetch (the inverse
+// uses the conjugates).
+template <int N, int C, int T, int L = 4>
+struct LdsFft2 {
+    using B = LdsFft<N, C, T, -1, C, L>;
+    static constexpr int NP = B::NP, RO = B::RO, BPTO = B::BPTO, EPT = B::EPT, SPAN = B::SPAN;
+    static constexpr int BUF = (B::SIZE + 1) & ~1;          // entries per buffer, 16-byte aligned
+    static constexpr int SIZE = 2 * BUF;
+    ISAM_DEV static constexpr int pad(int e) { return e + (e >> 4); }
+    static constexpr int nb(int pass) { return N / fft_radix(N, pass, L) * C; }
+    static constexpr int bpt(int pass) { return (nb(pass) + T - 1) / T; }
+    // register offset of pass p's twiddles (middle passes 1..NP-2, then the last pass)
+    static constexpr int tw_off(int pass) {
+        return pass <= 1 ? 0 : tw_off(pass - 1) + bpt(pass - 1) * (fft_radix(N, pass - 1, L) - 1);
+    }
+    static constexpr int NTW = NP <= 1 ? 1 : tw_off(NP - 1) + BPTO * (RO - 1);
+    struct Tw {
+        float2 w[NTW];
+    };
+
+    ISAM_DEV static bool outer(int tid, int i, int& c, int& b) { return B::outer(tid, i, c, b); }
+
+    template <int PASS>
+    ISAM_DEV static void load_mid(const float2* __restrict__ tw, int tid, Tw& t) {
+        if constexpr (PASS < NP - 1) {
+            constexpr int R = fft_radix(N, PASS, L), NS = fft_stride(N, PASS, L);
+            constexpr int OFF = fft_stage_off(N, PASS, L), TO = tw_off(PASS);
+#pragma unroll
+            for (int i = 0; i < bpt(PASS); ++i) {
+                const int f = tid + i * T;
+                const int k = (f / C) % NS;
+#pragma unroll
+                for (int j = 1; j < R; ++j)
+                    t.w[TO + i * (R - 1) + j - 1] =
+                        (nb(PASS) % T == 0 || f < nb(PASS)) ? tw[OFF + j * NS + k] : c2(0.f, 0.f);
+            }
+            load_mid<PASS + 1>(tw, tid, t);
+        }
+    }
+
+    // The twiddles thread tid applies, for every pass (table of exp(-2 pi i e / period)).
+    ISAM_DEV static void load(const float2* __restrict__ tw, int tid, Tw& t) {
+        if constexpr (NP > 1) {
+            load_mid<1>(tw, tid, t);
+            constexpr int OFF = fft_stage_off(N, NP - 1, L), TO = tw_off(NP - 1);
+#pragma unroll
+            for (int i = 0; i < BPTO; ++i) {
+                int c, b;
+                const bool ok = outer(tid, i, c, b);
+#pragma unroll
+                for (int j = 1; j < RO; ++j)
+                    t.w[TO + i * (RO - 1) + j - 1] = ok ? tw[OFF + j * SPAN + b] : c2(0.f, 0.f);
+            }
+        }
+    }
+
+    template <int SIGN>
+    ISAM_DEV static float2 apply(float2 x, float2 w) {
+        return cmul(x, SIGN > 0 ? cconj(w) : w);
+    }
+
+    template <int PASS, int SIGN>
+    ISAM_DEV static void middle(float2* lds, const Tw& t, int tid) {
+        if constexpr (PASS < NP - 1) {
+            constexpr int R = fft_radix(N, PASS, L), NS = fft_stride(N, PASS, L), TO = tw_off(PASS);
+            const float2* src = lds + ((PASS - 1) & 1) * BUF;
+            float2* dst = lds + (PASS & 1) * BUF;
+#pragma unroll
+            for (int i = 0; i < bpt(PASS); ++i) {
+                const int f = tid + i * T;
+                if ((nb(PASS) % T == 0) || f < nb(PASS)) {
+                    const int c = f % C, b = f / C;
+                    const int k = b % NS;
+                    float2 x[R];
+#pragma unroll
+                    for (int j = 0; j < R; ++j) x[j] = src[pad((b + j * (N / R)) * C + c)];
+#pragma unroll
+                    for (int j = 1; j < R; ++j) x[j] = apply<SIGN>(x[j], t.w[TO + i * (R - 1) + j - 1]);
+                    Dft<R, SIGN>::run(x);
+                    const int base = (b - k) * R + k;
+#pragma unroll
+                    for (int j = 0; j < R; ++j) dst[pad((base + j * NS) * C + c)] = x[j];
+                }
+            }
+            __syncthreads();
+            middle<PASS + 1, SIGN>(lds, t, tid);
+        }
+    }
+
+    // As LdsFft::run, over lds[0, SIZE).  With open = false the opening barrier is left out:
+    // the caller guarantees that no thread still reads buffer 0 (true after a transform of this
+    // type when NP is odd, since its last pass reads buffer 1).  The caller places a barrier
+    // before writing lds again afterwards.
+    template <int SIGN>
+    ISAM_DEV static void run(float2 (&v)[EPT], float2* lds, const Tw& t, int tid, bool open = true) {
+        if constexpr (NP == 0) {
+            return;
+        } else if constexpr (NP == 1) {
+#pragma unroll
+            for (int i = 0; i < BPTO; ++i) Dft<RO, SIGN>::run(&v[i * RO]);
+        } else {
+            if (open) __syncthreads();
+#pragma unroll
+            for (int i = 0; i < BPTO; ++i) {
+                int c, b;
+                if (outer(tid, i, c, b)) {
+                    Dft<RO, SIGN>::run(&v[i * RO]);
+#pragma unroll
+                    for (int j = 0; j < RO; ++j) lds[pad((b * RO + j) * C + c)] = v[i * RO + j];
+                }
+            }
+            __syncthreads();
+            middle<1, SIGN>(lds, t, tid);
+            const float2* src = lds + ((NP - 2) & 1) * BUF;
+            constexpr int TO = tw_off(NP - 1);
+#pragma unroll
+            for (int i = 0; i < BPTO; ++i) {
+                int c, b;
+                if (outer(tid, i, c, b)) {
+#pragma unroll
+                    for (int j = 0; j < RO; ++j) v[i * RO + j] = src[pad((b + j * SPAN) * C + c)];
+#pragma unroll
+                    for (int j = 1; j < RO; ++j) v[i * RO + j] = apply<SIGN>(v[i * RO + j], t.w[TO + i * (RO - 1) + j - 1]);
+                    Dft<RO, SIGN>::run(&v[i * RO]);
+                }
+            }
+        }
+    }
+};
+
+// LdsFft behind the interface of LdsFft2 (tiles too large for two buffers).
+template <int N, int C, int T, int L = 4>
+struct LdsFft1 {
+    using B = LdsFft<N, C, T, -1, C, L>;
+    static constexpr int NP = B::NP, RO = B::RO, BPTO = B::BPTO, EPT = B::EPT, SPAN = B::SPAN;
+    static constexpr int SIZE = B::SIZE;
+    struct Tw {
+        const float2* p;
+    };
+    ISAM_DEV static bool outer(int tid, int i, int& c, int& b) { return B::outer(tid, i, c, b); }
+    ISAM_DEV static void load(const float2* __restrict__ tw, int, Tw& t) { t.p = tw; }
+    template <int SIGN>
+    ISAM_DEV static void run(float2 (&v)[EPT], float2* lds, const Tw& t, int tid, bool /*open*/ = true) {
+        LdsFft<N, C, T, SIGN, C, L>::run(v, lds, t.p, tid);
+    }
+};
+
 }  // namespace isam

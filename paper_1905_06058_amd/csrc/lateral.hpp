@@ -18,6 +18,7 @@
 //                forward lateral transform of the next momentum point, with Eq. 15 norms
 #pragma once
 #include <algorithm>
+#include <type_traits>
 
 #include "common.hpp"
 #include "fft.hpp"
@@ -47,6 +48,16 @@ struct LatCfg {
     using Inv = LdsFft<N, C, T, +1, C, L>;
     static_assert(Fwd::EPT == Inv::EPT, "layouts");
     static_assert(LDS <= 160 * 1024, "lateral tile exceeds the LDS of one CU");
+    // FISTA update pass: the two-buffer form for tiles of 8192 points or more where two fit
+    // in LDS (smaller tiles keep the LDS that lets several workgroups share a CU).  Chained
+    // transforms skip the opening barrier when the last pass reads the second buffer (odd
+    // pass count).
+    static constexpr bool TWO = N * C >= 8192 && 2 * LDS <= 160 * 1024;
+    using F2 = std::conditional_t<TWO, LdsFft2<N, C, T, L>, LdsFft1<N, C, T, L>>;
+    static constexpr bool F2_OPEN = !TWO || F2::NP % 2 == 0;
+    static constexpr size_t LDS2 = (size_t)F2::SIZE * sizeof(float2) > 256 ? (size_t)F2::SIZE * sizeof(float2) : 256;
+    static_assert(F2::EPT == Fwd::EPT, "layouts");
+    static_assert(LDS2 <= 160 * 1024, "two-buffer lateral tile exceeds the LDS of one CU");
 };
 
 // IB / OB: input / output in the column-blocked layout (else row-major [nx][nk]).
@@ -242,12 +253,15 @@ ISAM_DEV void lat_fista_body(float2* __restrict__ eta_hat, const float2* __restr
                              const float2* __restrict__ tw, float scale, const FistaStep& fs,
                              float* __restrict__ partials, int tile, int ntiles) {
     using Cf = LatCfg<N, C>;
-    using FI = typename Cf::Inv;
-    using FF = typename Cf::Fwd;
+    using FI = typename Cf::F2;
+    using FF = typename Cf::F2;
     constexpr int RO = Cf::RO, SPAN = Cf::SPAN;
     if (fs.stop && *fs.stop) return;                   // solver already stopped (uniform)
     extern __shared__ float2 lds[];
     const int m0 = xcd_tile(tile, ntiles) * Cf::C;
+    // the twiddles of both transforms, fetched with the tile
+    typename FI::Tw twr;
+    FI::load(tw, threadIdx.x, twr);
     float2 v[FI::EPT];
     float2 gv[NORMS ? FI::EPT : 1];
 #pragma unroll
@@ -278,8 +292,8 @@ ISAM_DEV void lat_fista_body(float2* __restrict__ eta_hat, const float2* __restr
             }
         }
     }
-    FI::run(v, lds, tw, threadIdx.x);
-    if constexpr (NORMS) FI::run(gv, lds, tw, threadIdx.x);
+    FI::template run<+1>(v, lds, twr, threadIdx.x, false);      // nothing has read lds yet
+    if constexpr (NORMS) FI::template run<+1>(gv, lds, twr, threadIdx.x, Cf::F2_OPEN);
     float acc[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int i = 0; i < FI::BPTO; ++i) {
@@ -305,7 +319,7 @@ ISAM_DEV void lat_fista_body(float2* __restrict__ eta_hat, const float2* __restr
             }
         }
     }
-    FF::run(v, lds, tw, threadIdx.x);
+    FF::template run<-1>(v, lds, twr, threadIdx.x, Cf::F2_OPEN);
 #pragma unroll
     for (int i = 0; i < FF::BPTO; ++i) {
         int c, b;
@@ -398,12 +412,12 @@ hipError_t launch_fista(float2* eh, const float2* gh, float2* z, const float* w,
     const dim3 grid(nk / C, slabs);
     const float scale = 1.0f / sqrtf((float)N);
     if (fs.norms) {
-        set_lds(k_lat_fista<N, C, true>, Cf::LDS);
-        ISAM_LAUNCH((k_lat_fista<N, C, true>), grid, dim3(Cf::T), Cf::LDS, s, eh, gh, z, w, nk, tw,
+        set_lds(k_lat_fista<N, C, true>, Cf::LDS2);
+        ISAM_LAUNCH((k_lat_fista<N, C, true>), grid, dim3(Cf::T), Cf::LDS2, s, eh, gh, z, w, nk, tw,
                            scale, fs, partials, slab);
     } else {
-        set_lds(k_lat_fista<N, C, false>, Cf::LDS);
-        ISAM_LAUNCH((k_lat_fista<N, C, false>), grid, dim3(Cf::T), Cf::LDS, s, eh, gh, z, w, nk, tw,
+        set_lds(k_lat_fista<N, C, false>, Cf::LDS2);
+        ISAM_LAUNCH((k_lat_fista<N, C, false>), grid, dim3(Cf::T), Cf::LDS2, s, eh, gh, z, w, nk, tw,
                            scale, fs, partials, slab);
     }
     return hipGetLastError();
@@ -445,11 +459,11 @@ hipError_t launch_fista_batch(int norms, const LatScan* recs, const int2* map, i
                               hipStream_t s) {
     using Cf = LatCfg<N, C>;
     if (norms) {
-        set_lds(k_lat_fista_batch<N, C, true>, Cf::LDS);
-        hipLaunchKernelGGL((k_lat_fista_batch<N, C, true>), dim3(nblk), dim3(Cf::T), Cf::LDS, s, recs, map, beta);
+        set_lds(k_lat_fista_batch<N, C, true>, Cf::LDS2);
+        hipLaunchKernelGGL((k_lat_fista_batch<N, C, true>), dim3(nblk), dim3(Cf::T), Cf::LDS2, s, recs, map, beta);
     } else {
-        set_lds(k_lat_fista_batch<N, C, false>, Cf::LDS);
-        hipLaunchKernelGGL((k_lat_fista_batch<N, C, false>), dim3(nblk), dim3(Cf::T), Cf::LDS, s, recs, map, beta);
+        set_lds(k_lat_fista_batch<N, C, false>, Cf::LDS2);
+        hipLaunchKernelGGL((k_lat_fista_batch<N, C, false>), dim3(nblk), dim3(Cf::T), Cf::LDS2, s, recs, map, beta);
     }
     return hipGetLastError();
 }
