@@ -48,12 +48,16 @@ struct LatCfg {
     using Inv = LdsFft<N, C, T, +1, C, L>;
     static_assert(Fwd::EPT == Inv::EPT, "layouts");
     static_assert(LDS <= 160 * 1024, "lateral tile exceeds the LDS of one CU");
-    // FISTA update pass: the two-buffer form for tiles of 8192 points or more where two fit
-    // in LDS (smaller tiles keep the LDS that lets several workgroups share a CU).  Chained
-    // transforms skip the opening barrier when the last pass reads the second buffer (odd
-    // pass count).
-    static constexpr bool TWO = N * C >= 8192 && 2 * LDS <= 160 * 1024;
-    using F2 = std::conditional_t<TWO, LdsFft2<N, C, T, L>, LdsFft1<N, C, T, L>>;
+    // The two-buffer form for tiles of 4096 points or more and at most 8 lanes, where two
+    // fit in LDS: the x transforms of B-scans, whose few large tiles leave one workgroup per
+    // CU anyway.  Smaller tiles, and the wide tiles of a volume's y transform, keep the LDS
+    // that lets several workgroups share a CU.  Chained transforms skip the opening barrier
+    // when the last pass reads the second buffer (odd pass count).  The transform of a
+    // row-major input keeps one buffer (FX<false>): it measured slower with two.
+    static constexpr bool TWO = N * C >= 4096 && C <= 8 && 2 * LDS <= 160 * 1024;
+    template <bool USE>
+    using FX = std::conditional_t<USE && TWO, LdsFft2<N, C, T, L>, LdsFft1<N, C, T, L>>;
+    using F2 = FX<true>;
     static constexpr bool F2_OPEN = !TWO || F2::NP % 2 == 0;
     static constexpr size_t LDS2 = (size_t)F2::SIZE * sizeof(float2) > 256 ? (size_t)F2::SIZE * sizeof(float2) : 256;
     static_assert(F2::EPT == Fwd::EPT, "layouts");
@@ -65,9 +69,11 @@ template <int N, int C, int SIGN, bool IB, bool OB>
 ISAM_DEV void lat_c2c_body(const float2* in, float2* out, int nk, const float2* __restrict__ tw, float scale,
                            int tile, int ntiles) {
     using Cf = LatCfg<N, C>;
-    using F = LdsFft<N, Cf::C, Cf::T, SIGN, Cf::C, Cf::L>;
+    using F = typename Cf::template FX<IB>;
     extern __shared__ float2 lds[];
     const int m0 = xcd_tile(tile, ntiles) * Cf::C;
+    typename F::Tw twr;
+    F::load(tw, threadIdx.x, twr);
     float2 v[F::EPT];
 #pragma unroll
     for (int i = 0; i < F::BPTO; ++i) {
@@ -78,7 +84,7 @@ ISAM_DEV void lat_c2c_body(const float2* in, float2* out, int nk, const float2* 
                 v[i * Cf::RO + j] = in[IB ? blk(b + j * Cf::SPAN, m0 + c, N) : (unsigned)(b + j * Cf::SPAN) * nk + m0 + c];
         }
     }
-    F::run(v, lds, tw, threadIdx.x);
+    F::template run<SIGN>(v, lds, twr, threadIdx.x, false);      // nothing has read lds yet
 #pragma unroll
     for (int i = 0; i < F::BPTO; ++i) {
         int c, b;
@@ -151,9 +157,11 @@ template <int N, int C>
 ISAM_DEV void lat_c2r_body(const float2* __restrict__ zh, float* __restrict__ s, int nk,
                            const float2* __restrict__ tw, float scale, int tile, int ntiles) {
     using Cf = LatCfg<N, C>;
-    using F = typename Cf::Inv;
+    using F = typename Cf::F2;
     extern __shared__ float2 lds[];
     const int n0 = xcd_tile(tile, ntiles) * 2 * Cf::C;
+    typename F::Tw twr;
+    F::load(tw, threadIdx.x, twr);
     float2 v[F::EPT];
 #pragma unroll
     for (int i = 0; i < F::BPTO; ++i) {
@@ -164,7 +172,7 @@ ISAM_DEV void lat_c2r_body(const float2* __restrict__ zh, float* __restrict__ s,
                 v[i * Cf::RO + j] = hermitian_pair<N>(zh, b + j * Cf::SPAN, n0 + 2 * c);
         }
     }
-    F::run(v, lds, tw, threadIdx.x);
+    F::template run<+1>(v, lds, twr, threadIdx.x, false);
 #pragma unroll
     for (int i = 0; i < F::BPTO; ++i) {
         int c, b;
@@ -200,9 +208,11 @@ template <int N, int C>
 ISAM_DEV void lat_r2c_body(const float* __restrict__ r, float2* __restrict__ rh, int nk,
                            const float2* __restrict__ tw, float scale, int tile, int ntiles) {
     using Cf = LatCfg<N, C>;
-    using F = typename Cf::Fwd;
+    using F = typename Cf::F2;
     extern __shared__ float2 lds[];
     const int n0 = xcd_tile(tile, ntiles) * 2 * Cf::C;
+    typename F::Tw twr;
+    F::load(tw, threadIdx.x, twr);
     float2 v[F::EPT];
 #pragma unroll
     for (int i = 0; i < F::BPTO; ++i) {
@@ -214,7 +224,7 @@ ISAM_DEV void lat_r2c_body(const float* __restrict__ r, float2* __restrict__ rh,
                     *reinterpret_cast<const float2*>(r + (unsigned)(b + j * Cf::SPAN) * nk + n0 + 2 * c);
         }
     }
-    F::run(v, lds, tw, threadIdx.x);
+    F::template run<-1>(v, lds, twr, threadIdx.x, false);
     split_store<N, Cf::T, Cf::C, Cf::L>(lds, v, rh, nk, n0, scale);
 }
 
@@ -378,8 +388,8 @@ hipError_t launch_c2c(const float2* in, float2* out, int nk, const float2* tw, i
         ISAM_LAUNCH((k_lat_c2c<N, C, -1, false, true>), grid, dim3(Cf::T), Cf::LDS, s, in, out, nk, tw, scale,
                     slab_in, slab_out);
     } else {
-        set_lds(k_lat_c2c<N, C, +1, true, false>, Cf::LDS);
-        ISAM_LAUNCH((k_lat_c2c<N, C, +1, true, false>), grid, dim3(Cf::T), Cf::LDS, s, in, out, nk, tw, scale,
+        set_lds(k_lat_c2c<N, C, +1, true, false>, Cf::LDS2);
+        ISAM_LAUNCH((k_lat_c2c<N, C, +1, true, false>), grid, dim3(Cf::T), Cf::LDS2, s, in, out, nk, tw, scale,
                     slab_in, slab_out);
     }
     return hipGetLastError();
@@ -389,8 +399,8 @@ template <int N, int C>
 hipError_t launch_c2r(const float2* zh, float* sout, int nk, const float2* tw, hipStream_t s, int slabs,
                       unsigned slab_in, unsigned slab_out) {
     using Cf = LatCfg<N, C>;
-    set_lds(k_lat_c2r<N, C>, Cf::LDS);
-    ISAM_LAUNCH((k_lat_c2r<N, C>), dim3(nk / (2 * C), slabs), dim3(Cf::T), Cf::LDS, s, zh, sout, nk, tw,
+    set_lds(k_lat_c2r<N, C>, Cf::LDS2);
+    ISAM_LAUNCH((k_lat_c2r<N, C>), dim3(nk / (2 * C), slabs), dim3(Cf::T), Cf::LDS2, s, zh, sout, nk, tw,
                        1.0f / sqrtf((float)N), slab_in, slab_out);
     return hipGetLastError();
 }
@@ -399,8 +409,8 @@ template <int N, int C>
 hipError_t launch_r2c(const float* r, float2* rh, int nk, const float2* tw, hipStream_t s, int slabs,
                       unsigned slab_in, unsigned slab_out) {
     using Cf = LatCfg<N, C>;
-    set_lds(k_lat_r2c<N, C>, Cf::LDS);
-    ISAM_LAUNCH((k_lat_r2c<N, C>), dim3(nk / (2 * C), slabs), dim3(Cf::T), Cf::LDS, s, r, rh, nk, tw,
+    set_lds(k_lat_r2c<N, C>, Cf::LDS2);
+    ISAM_LAUNCH((k_lat_r2c<N, C>), dim3(nk / (2 * C), slabs), dim3(Cf::T), Cf::LDS2, s, r, rh, nk, tw,
                        1.0f / sqrtf((float)N), slab_in, slab_out);
     return hipGetLastError();
 }
@@ -432,8 +442,8 @@ hipError_t launch_c2c_batch(const LatScan* recs, const int2* map, int nblk, int 
         set_lds(k_lat_c2c_batch<N, C, -1, false, true>, Cf::LDS);
         hipLaunchKernelGGL((k_lat_c2c_batch<N, C, -1, false, true>), dim3(nblk), dim3(Cf::T), Cf::LDS, s, recs, map);
     } else {
-        set_lds(k_lat_c2c_batch<N, C, +1, true, false>, Cf::LDS);
-        hipLaunchKernelGGL((k_lat_c2c_batch<N, C, +1, true, false>), dim3(nblk), dim3(Cf::T), Cf::LDS, s, recs, map);
+        set_lds(k_lat_c2c_batch<N, C, +1, true, false>, Cf::LDS2);
+        hipLaunchKernelGGL((k_lat_c2c_batch<N, C, +1, true, false>), dim3(nblk), dim3(Cf::T), Cf::LDS2, s, recs, map);
     }
     return hipGetLastError();
 }
@@ -441,16 +451,16 @@ hipError_t launch_c2c_batch(const LatScan* recs, const int2* map, int nblk, int 
 template <int N, int C>
 hipError_t launch_c2r_batch(const LatScan* recs, const int2* map, int nblk, hipStream_t s) {
     using Cf = LatCfg<N, C>;
-    set_lds(k_lat_c2r_batch<N, C>, Cf::LDS);
-    hipLaunchKernelGGL((k_lat_c2r_batch<N, C>), dim3(nblk), dim3(Cf::T), Cf::LDS, s, recs, map);
+    set_lds(k_lat_c2r_batch<N, C>, Cf::LDS2);
+    hipLaunchKernelGGL((k_lat_c2r_batch<N, C>), dim3(nblk), dim3(Cf::T), Cf::LDS2, s, recs, map);
     return hipGetLastError();
 }
 
 template <int N, int C>
 hipError_t launch_r2c_batch(const LatScan* recs, const int2* map, int nblk, hipStream_t s) {
     using Cf = LatCfg<N, C>;
-    set_lds(k_lat_r2c_batch<N, C>, Cf::LDS);
-    hipLaunchKernelGGL((k_lat_r2c_batch<N, C>), dim3(nblk), dim3(Cf::T), Cf::LDS, s, recs, map);
+    set_lds(k_lat_r2c_batch<N, C>, Cf::LDS2);
+    hipLaunchKernelGGL((k_lat_r2c_batch<N, C>), dim3(nblk), dim3(Cf::T), Cf::LDS2, s, recs, map);
     return hipGetLastError();
 }
 
