@@ -355,6 +355,31 @@ def test_fista_mixed_radix_lateral_length(P):
     assert rel(z, ref.z) < TOL_FISTA
 
 
+@pytest.mark.parametrize("nx", [768, 1024])
+def test_fista_wide_lateral_tiles(P, nx):
+    """Lateral tiles of 8 lanes x nx >= 4096 points run the update pass with two LDS buffers:
+    nx = 1024 has an odd pass count (chained transforms skip the opening barrier), nx = 768
+    (3 x 256) an even one with more butterflies than threads in its outer passes.  40 FISTA
+    iterations (the device stop check, with its extra transform, runs every 16) against the
+    oracle."""
+    nk = 64
+    o = ph.custom_optics(nx, nk, edge_phase2=12 * math.pi, edge_phase3=2 * math.pi, focus_rows=9)
+    g = O.Geometry.of(o)
+    rng = np.random.default_rng(nx)
+    eta = ph.layers(rng, nx, nk, 2) + ph.point_scatterers(rng, nx, nk, nx // 8)
+    op = O.Operator(g, "N")
+    y = ph.add_noise(op.A(eta), 25.0, nx)
+    with make_plan(P, o) as plan:
+        L = plan.lipschitz(iters=50, seed=0)
+        lam = 0.05 * plan.lambda_max(to_dev(y))
+        res = plan.fista(to_dev(y), lam, 40, L=L, tol=1e-12)
+        z = to_host(res.eta)
+    ref = O.fista(op, y, lam, L, 40)
+    assert res.iters == 40
+    assert rel(z, ref.z) < TOL_FISTA
+    assert abs(res.resid2 - ref.resid2[-1]) < 1e-4 * ref.resid2[-1]
+
+
 def test_fista_tiny_weighted_stop_and_residual(P):
     """Depth weights (MBIR+), the Eq. 15 stop and the residual add-back of Alg. 1.
 
