@@ -389,7 +389,8 @@ __global__ __launch_bounds__(2 * NuCfg<K>::T) void k_nufft_calgrad(const float2*
     block_sum_store<2 * Cf::T, 3>(acc, reinterpret_cast<float*>(smem), partials + b * kRedSlots);
 }
 
-// Clears the chunk's slot arrays ([3][SLOTC] float2) with 16-byte stores.
+// Clears a half's slot arrays ([3][SLOTC] float2) with 16-byte stores (once, before the first
+// chunk; afterwards each cell's reader clears its triple).
 template <typename Cf>
 ISAM_DEV void zero_slots(float2* SL, int tid) {
     constexpr int N2 = 3 * Cf::SLOTC, N4 = N2 / 2;
@@ -415,7 +416,9 @@ ISAM_DEV void zero_slots(float2* SL, int tid) {
 // cell g0_n + 1 + j.  Two samples that reach one cell differ in g0 by at least 2, so they
 // never share a slot: each slot has one writer.  Each cell then sums its three slots (in
 // slot order) into Y'[cell mod K]; chunks follow one another, so every sum is formed in a
-// fixed order and the result is bitwise repeatable.
+// fixed order and the result is bitwise repeatable.  A triple has one reader too (the
+// thread that owns the cell), which clears it after reading: a chunk then needs two
+// barriers (chunk base, scatter), since the next chunk's scatter comes after its first.
 //
 // Block = two halves of T threads; half h owns column h of the pair (its slots, its Y' in
 // registers, its inverse FFT).  Partners share q^2, hence their Stolt points and weights:
@@ -460,6 +463,7 @@ ISAM_DEV void nufft_adj_body(const float2* __restrict__ rh, float2* __restrict__
     float2 v[F::EPT];
 #pragma unroll
     for (int e = 0; e < F::EPT; ++e) v[e] = c2(0.f, 0.f);
+    zero_slots<Cf>(SL, tid);
     for (int ch = 0; ch < Cf::NCH; ++ch) {
         const int n = ch * Cf::CS + tid;
         const bool mine = live && tid < Cf::CS;
@@ -480,7 +484,6 @@ ISAM_DEV void nufft_adj_body(const float2* __restrict__ rh, float2* __restrict__
         const unsigned long long pm = __ballot(prop);
         const int g0w = pm ? __builtin_amdgcn_readlane(g0v, (int)__builtin_ctzll(pm)) : 0x7fffffff;
         if ((tid & 63) == 0) s_red[half][tid >> 6] = g0w;
-        zero_slots<Cf>(SL, tid);
         __syncthreads();
         int cbase = s_red[half][0];
 #pragma unroll
@@ -531,12 +534,12 @@ ISAM_DEV void nufft_adj_body(const float2* __restrict__ rh, float2* __restrict__
                         if (c < Cf::SLOTC) {
                             const float2 s0 = SL[c], s1 = SL[Cf::SLOTC + c], s2 = SL[2 * Cf::SLOTC + c];
                             v[i * Cf::RO + j] = cadd(v[i * Cf::RO + j], cadd(cadd(s0, s1), s2));
+                            SL[c] = SL[Cf::SLOTC + c] = SL[2 * Cf::SLOTC + c] = c2(0.f, 0.f);
                         }
                     }
                 }
             }
         }
-        __syncthreads();
     }
     F::run(v, Y, a.tw8, tid);         // opens with a barrier: the last reads of the slots are done
     if (!live) return;
