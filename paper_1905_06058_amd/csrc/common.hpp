@@ -37,6 +37,11 @@ ISAM_DEV float2 cfmac(float2 a, float2 b, float2 acc) {
     return acc;
 }
 ISAM_DEV float cabs2(float2 a) { return fmaf(a.x, a.x, a.y * a.y); }
+// The FISTA gradient step eta - step * g (Alg. 1), one fused multiply-add per component:
+// the adjoint's epilogue and the update pass form it alike.
+ISAM_DEV float2 grad_step(float2 eta, float2 g, float step) {
+    return make_float2(fmaf(-step, g.x, eta.x), fmaf(-step, g.y, eta.y));
+}
 
 // 64-wide wavefront sum by butterfly shuffles.
 ISAM_DEV float wave_sum(float v) {

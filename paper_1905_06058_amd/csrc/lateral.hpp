@@ -281,9 +281,13 @@ ISAM_DEV void lat_fista_body(float2* __restrict__ eta_hat, const float2* __restr
 #pragma unroll
             for (int j = 0; j < RO; ++j) {
                 const size_t off = blk(b + j * SPAN, m0 + c, N);
-                const float2 g = cscale(ghat[off], fs.step);
-                v[i * RO + j] = csub(eta_hat[off], g);          // u_hat = eta_hat - step * g_hat
-                if constexpr (NORMS) gv[i * RO + j] = g;
+                // u_hat = eta_hat - step * g_hat, or as the adjoint already formed it
+                if (!NORMS && fs.pre) {
+                    v[i * RO + j] = ghat[off];
+                } else {
+                    v[i * RO + j] = grad_step(eta_hat[off], ghat[off], fs.step);
+                    if constexpr (NORMS) gv[i * RO + j] = cscale(ghat[off], fs.step);
+                }
             }
         }
     }

@@ -425,6 +425,9 @@ ISAM_DEV void zero_slots(float2* SL, int tid) {
 // both halves take the same samples and half h evaluates taps 3h .. 3h + 2 for both
 // columns.  Self-paired columns have their own q^2; each half then runs its own column
 // with all J taps.
+//
+// In the FISTA loop (a.step_eta set) the output is the gradient step eta_hat - gstep g_hat
+// of Alg. 1 rather than g_hat, so the update pass reads one array instead of two.
 template <int K>
 ISAM_DEV void nufft_adj_body(const float2* __restrict__ rh, float2* __restrict__ ghat, const NufftArgs& a,
                              int bidx, int nblk) {
@@ -551,7 +554,11 @@ ISAM_DEV void nufft_adj_body(const float2* __restrict__ rh, float2* __restrict__
             for (int j = 0; j < Cf::RO; ++j) {
                 const int x = b + j * Cf::SPAN;
                 const int u = (x + a.mi + a.nk / 2) & (K - 1);
-                if (u < a.nk) ghat[blk(col, u, a.ncol)] = cscale(v[i * Cf::RO + j], a.sm[u]);
+                if (u < a.nk) {
+                    const unsigned o = blk(col, u, a.ncol);
+                    const float2 g = cscale(v[i * Cf::RO + j], a.sm[u]);
+                    ghat[o] = a.step_eta ? grad_step(a.step_eta[o], g, a.gstep) : g;
+                }
             }
         }
     }
@@ -601,11 +608,14 @@ hipError_t launch_calgrad(const isam_plan_s* p, const float2* etahat, const floa
 }
 
 template <int K>
-hipError_t launch_adj(const isam_plan_s* p, const float2* rh, float2* ghat, hipStream_t s, const int* stop) {
+hipError_t launch_adj(const isam_plan_s* p, const float2* rh, float2* ghat, hipStream_t s, const int* stop,
+                      const float2* step_eta, float gstep) {
     using Cf = NuAdjCfg<K>;
     set_lds(k_nufft_adj<K>, Cf::LDS);
     NufftArgs a = p->nufft_args();
     a.stop = stop;
+    a.step_eta = step_eta;
+    a.gstep = gstep;
     ISAM_LAUNCH(k_nufft_adj<K>, dim3(nufft_adj_blocks(p)), dim3(2 * Cf::T), Cf::LDS, s, rh, ghat, a);
     return hipGetLastError();
 }
@@ -650,8 +660,9 @@ hipError_t nufft_calgrad(const isam_plan_s* p, const float2* etahat, const float
     ISAM_K_SWITCH(p->K, return launch_calgrad<K>(p, etahat, ghalf, partials, s));
 }
 
-hipError_t nufft_adj(const isam_plan_s* p, const float2* rh, float2* ghat, hipStream_t s, const int* stop) {
-    ISAM_K_SWITCH(p->K, return launch_adj<K>(p, rh, ghat, s, stop));
+hipError_t nufft_adj(const isam_plan_s* p, const float2* rh, float2* ghat, hipStream_t s, const int* stop,
+                     const float2* step_eta, float gstep) {
+    ISAM_K_SWITCH(p->K, return launch_adj<K>(p, rh, ghat, s, stop, step_eta, gstep));
 }
 
 hipError_t nufft_fwd_batch(int K_, const NuScan* recs, const int2* map, int nblk, hipStream_t s) {

@@ -59,6 +59,10 @@ struct NufftArgs {
     int ncol;               // lateral-frequency columns (nx for a B-scan, nx * ny for a volume)
     int nhalf;              // columns of the Hermitian half arrays (nx/2 + 1, times ny)
     const FwdPair* pairs;   // NUFFT (forward and adjoint): column pair of each workgroup
+    // adjoint only: with step_eta set, the output is the FISTA gradient step
+    // step_eta - gstep * g_hat instead of g_hat
+    const float2* step_eta = nullptr;
+    float gstep = 0.f;
 };
 
 
@@ -76,6 +80,7 @@ struct FistaStep {
     float step, lam, beta;
     int norms;
     const int* stop;     // solver stop flag (non-zero: return at once), or null
+    int pre = 0;         // ghat already holds eta_hat - step * g_hat (formed by the adjoint)
 };
 
 // Operands of one scan in a batched NUFFT pass (forward: in = eta_hat, in2 = F(y) or null,
@@ -211,8 +216,9 @@ int fista_finish(isam_plan_t p, double L, int add_residual, float2* out, hipStre
 bool lat_supported(int nx);
 int nufft_fwd_blocks(const isam_plan_s* p);
 int nufft_adj_blocks(const isam_plan_s* p);
+// Adjoint Stolt NUFFT: ghat = g_hat, or with step_eta the gradient step step_eta - gstep g_hat.
 hipError_t nufft_adj(const isam_plan_s* p, const float2* rh, float2* ghat, hipStream_t s,
-                     const int* stop = nullptr);
+                     const int* stop = nullptr, const float2* step_eta = nullptr, float gstep = 0.f);
 hipError_t nufft_calgrad(const isam_plan_s* p, const float2* etahat, const float2* ghalf, float* partials,
                          hipStream_t s);
 int nufft_span_ok(const isam_plan_s* p);          // host check of the Stolt span bound

@@ -471,6 +471,10 @@ extern "C" int isam_fista(isam_plan_t p, const float* y, float lambda, const flo
     fs.step = (float)(1.0 / L);
     fs.lam = lambda;
     fs.norms = tol > 0.f;
+    // Without the Eq. 15 norms (which need g_hat itself) the adjoint of a B-scan writes the
+    // gradient step eta_hat - g_hat / L, so the update pass reads one array instead of two.
+    // (A volume's adjoint output still passes through its y transform first.)
+    fs.pre = !fs.norms && p->ny == 1;
     // With a tolerance, Eq. 15 is evaluated on the device after every update pass; once it
     // holds, every later solver kernel returns at once, so the state stays that of the
     // stopping iteration.  The host reads the stop state every kPoll iterations.
@@ -490,7 +494,7 @@ extern "C" int isam_fista(isam_plan_t p, const float* y, float lambda, const flo
             eh = p->etahat;
         }
         TIMED(1, nufft_fwd(p, eh, p->yhat, p->rh, part_r, s, stop));
-        TIMED(4, nufft_adj(p, p->rh, p->ghat, s, stop));
+        TIMED(4, nufft_adj(p, p->rh, p->ghat, s, stop, fs.pre ? p->fista_hat : nullptr, fs.step));
         const float2* gx = p->ghat;
         if (vol) {
             TIMED(7, lat_c2c_y(p, p->ghat, p->xs, p->nx * p->nk, +1, s));
