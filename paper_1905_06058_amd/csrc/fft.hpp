@@ -286,12 +286,17 @@ struct LdsFft {
     // opens with a barrier (earlier readers of lds are done), and the caller must place a
     // barrier before writing lds again afterwards.
     ISAM_DEV static void run(float2 (&v)[EPT], float2* lds, const float2* tw, int tid) {
-        if constexpr (NP == 0) {
-            return;
-        } else if constexpr (NP == 1) {
+        run_head(v, lds, tw, tid);
+        run_tail(v, lds, tw, tid);
+    }
+
+    // run() in two parts: every pass but the last (the data then sit in lds and v is free),
+    // and the last pass (lds back to v), so that a caller can issue loads in between.
+    ISAM_DEV static void run_head(float2 (&v)[EPT], float2* lds, const float2* tw, int tid) {
+        if constexpr (NP == 1) {
 #pragma unroll
             for (int i = 0; i < BPTO; ++i) Dft<RO, SIGN>::run(&v[i * RO]);
-        } else {
+        } else if constexpr (NP > 1) {
             // first pass: no twiddles (stride 1), write Stockham order b*RO + j
             __syncthreads();
 #pragma unroll
@@ -305,6 +310,11 @@ struct LdsFft {
             }
             __syncthreads();
             middle<1>(lds, tw, tid);
+        }
+    }
+
+    ISAM_DEV static void run_tail(float2 (&v)[EPT], float2* lds, const float2* tw, int tid) {
+        if constexpr (NP > 1) {
             // last pass: stride N/RO, twiddle exponent j*b, result stays in registers
 #pragma unroll
             for (int i = 0; i < BPTO; ++i) {

@@ -73,6 +73,10 @@ struct NuAdjCfg {
     static constexpr int BPC = (int)((160 * 1024) / LDS);
     static constexpr int WPE_LDS = BPC * (2 * T / 64) / 4;
     static constexpr int WPE = WPE_LDS > 8 ? 8 : (WPE_LDS < 1 ? 1 : WPE_LDS);
+    // the epilogue's operands fetched ahead of the last FFT pass: measured at K = 4096, whose
+    // register budget holds them; at other lengths they spill (K = 2048) or cost occupancy
+    // (K = 8192), so those keep one load per output
+    static constexpr bool EPI_AHEAD = K == 4096;
 };
 
 // Stolt grid position of sample n of a column with q^2 = q2 (FP64).  Returns false on an
@@ -544,7 +548,42 @@ ISAM_DEV void nufft_adj_body(const float2* __restrict__ rh, float2* __restrict__
             }
         }
     }
-    F::run(v, Y, a.tw8, tid);         // opens with a barrier: the last reads of the slots are done
+    F::run_head(v, Y, a.tw8, tid);    // opens with a barrier: the last reads of the slots are done
+    // With EPI_AHEAD the epilogue's operands are fetched while the last pass runs (v is free
+    // here: the data sit in LDS), so their latency hides behind the pass.
+    static_assert(2 * Cf::NK == K, "the depth spectrum fills half of the oversampled grid");
+    constexpr bool AH = Cf::EPI_AHEAD;
+    // eta_hat of the gradient step
+    float2 eh[AH ? F::EPT : 1];
+    if (AH && a.step_eta && live) {
+#pragma unroll
+        for (int i = 0; i < F::BPTO; ++i) {
+            int cc, b;
+            if (F::outer(tid, i, cc, b)) {
+#pragma unroll
+                for (int j = 0; j < Cf::RO; ++j) {
+                    const int u = (b + j * Cf::SPAN + a.mi + a.nk / 2) & (K - 1);
+                    eh[AH ? i * Cf::RO + j : 0] = u < a.nk ? a.step_eta[blk(col, u, a.ncol)] : c2(0.f, 0.f);
+                }
+            }
+        }
+    }
+    // the Kaiser-Bessel scales of the outputs kept: the depth indices u of a butterfly's RO
+    // outputs share their residue mod K / RO, and (nk = K / 2) the RO / 2 of them below nk
+    // are u = m K / RO + that residue, m < RO / 2.  Fetched at those indices, the loads issue
+    // together rather than one per output branch.
+    float smc[AH ? F::BPTO : 1][Cf::RO / 2];
+    if constexpr (AH) {
+#pragma unroll
+        for (int i = 0; i < F::BPTO; ++i) {
+            int cc, b;
+            F::outer(tid, i, cc, b);
+            const int r = (b + a.mi + a.nk / 2) & (Cf::SPAN - 1);
+#pragma unroll
+            for (int m = 0; m < Cf::RO / 2; ++m) smc[i][m] = a.sm[m * Cf::SPAN + r];
+        }
+    }
+    F::run_tail(v, Y, a.tw8, tid);
     if (!live) return;
 #pragma unroll
     for (int i = 0; i < F::BPTO; ++i) {
@@ -556,8 +595,18 @@ ISAM_DEV void nufft_adj_body(const float2* __restrict__ rh, float2* __restrict__
                 const int u = (x + a.mi + a.nk / 2) & (K - 1);
                 if (u < a.nk) {
                     const unsigned o = blk(col, u, a.ncol);
-                    const float2 g = cscale(v[i * Cf::RO + j], a.sm[u]);
-                    ghat[o] = a.step_eta ? grad_step(a.step_eta[o], g, a.gstep) : g;
+                    float sc;
+                    if constexpr (AH) {
+                        const int m = u / Cf::SPAN;
+                        sc = smc[i][0];
+#pragma unroll
+                        for (int mm = 1; mm < Cf::RO / 2; ++mm) sc = m == mm ? smc[i][mm] : sc;
+                    } else {
+                        sc = a.sm[u];
+                    }
+                    const float2 g = cscale(v[i * Cf::RO + j], sc);
+                    if (a.step_eta) ghat[o] = grad_step(AH ? eh[AH ? i * Cf::RO + j : 0] : a.step_eta[o], g, a.gstep);
+                    else ghat[o] = g;
                 }
             }
         }
