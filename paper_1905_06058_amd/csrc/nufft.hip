@@ -73,9 +73,10 @@ struct NuAdjCfg {
     static constexpr int BPC = (int)((160 * 1024) / LDS);
     static constexpr int WPE_LDS = BPC * (2 * T / 64) / 4;
     static constexpr int WPE = WPE_LDS > 8 ? 8 : (WPE_LDS < 1 ? 1 : WPE_LDS);
-    // the epilogue's operands fetched ahead of the last FFT pass: measured at K = 4096, whose
-    // register budget holds them; at other lengths they spill (K = 2048) or cost occupancy
-    // (K = 8192), so those keep one load per output
+    // operands fetched ahead of their use (the epilogue's before the last FFT pass, and in
+    // the single-scan kernel the modulation factors at the start): measured at K = 4096,
+    // whose register budget holds them; at other lengths, and for the modulation factors in
+    // the batched kernel, they spill (K = 2048) or cost occupancy (K = 8192)
     static constexpr bool EPI_AHEAD = K == 4096;
 };
 
@@ -432,7 +433,9 @@ ISAM_DEV void zero_slots(float2* SL, int tid) {
 //
 // In the FISTA loop (a.step_eta set) the output is the gradient step eta_hat - gstep g_hat
 // of Alg. 1 rather than g_hat, so the update pass reads one array instead of two.
-template <int K>
+// EN_AHEAD: the modulation factors E_n of the thread's samples are fetched with its residual
+// samples at the start, rather than in each chunk where the Stolt point is known.
+template <int K, bool EN_AHEAD>
 ISAM_DEV void nufft_adj_body(const float2* __restrict__ rh, float2* __restrict__ ghat, const NufftArgs& a,
                              int bidx, int nblk) {
     using Cf = NuAdjCfg<K>;
@@ -460,11 +463,12 @@ ISAM_DEV void nufft_adj_body(const float2* __restrict__ rh, float2* __restrict__
     // samples, fetched up front.  The partner of a pair reads its own row
     // when it is stored (a volume's lx = 0 or nx/2 plane), else the conjugate of pr.a's.
     const int row0 = pair || !live || half == 0 ? pr.ha : pr.hb;
-    float2 xr0[Cf::NCH];
+    float2 xr0[Cf::NCH], en0[EN_AHEAD ? Cf::NCH : 1];
 #pragma unroll
     for (int ch = 0; ch < Cf::NCH; ++ch) {
         const int n = min(ch * Cf::CS + tid, a.nk - 1);
         xr0[ch] = live ? rh[blk(row0, n, a.nhalf)] : c2(0.f, 0.f);
+        if constexpr (EN_AHEAD) en0[ch] = a.En[n];
     }
     // Y'[x] for the cells x = b + j K / RO this thread starts the inverse FFT from
     float2 v[F::EPT];
@@ -480,7 +484,7 @@ ISAM_DEV void nufft_adj_body(const float2* __restrict__ rh, float2* __restrict__
         const bool prop = mine && stolt_point(a, q2, n, t, fl, tau);
         float2 v0 = c2(0.f, 0.f), v1 = c2(0.f, 0.f);
         if (prop) {
-            const float2 m = modulation(a, a.En[n], Bl, t);
+            const float2 m = modulation(a, EN_AHEAD ? en0[EN_AHEAD ? ch : 0] : a.En[n], Bl, t);
             v0 = cmulc(xr0[ch], m);
             if (pair) v1 = cmulc(pr.hb >= 0 ? rh[blk(pr.hb, n, a.nhalf)] : cconj(xr0[ch]), m);
         }
@@ -616,7 +620,7 @@ ISAM_DEV void nufft_adj_body(const float2* __restrict__ rh, float2* __restrict__
 template <int K>
 __global__ __launch_bounds__(2 * NuAdjCfg<K>::T, NuAdjCfg<K>::WPE) void k_nufft_adj(const float2* __restrict__ rh,
                                                               float2* __restrict__ ghat, NufftArgs a) {
-    nufft_adj_body<K>(rh, ghat, a, blockIdx.x, gridDim.x);
+    nufft_adj_body<K, NuAdjCfg<K>::EPI_AHEAD>(rh, ghat, a, blockIdx.x, gridDim.x);
 }
 
 template <int K>
@@ -625,7 +629,7 @@ __global__ __launch_bounds__(2 * NuAdjCfg<K>::T, NuAdjCfg<K>::WPE) void k_nufft_
     const int2 m = map[blockIdx.x];
     if (m.x < 0) return;                               // padding entry (uniform)
     const NuScan& sc = scans[m.x];
-    nufft_adj_body<K>(sc.in, sc.out, sc.a, m.y, sc.nblk);
+    nufft_adj_body<K, false>(sc.in, sc.out, sc.a, m.y, sc.nblk);      // registers: no room
 }
 
 template <typename Kern>
