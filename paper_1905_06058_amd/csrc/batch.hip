@@ -532,8 +532,14 @@ extern "C" int isam_batch_fista(isam_batch_t b, const float* y, const float* lam
         f.fs.beta = 0.f;
         f.fs.norms = norms;
         f.fs.stop = norms ? &b->stops[i].iter : nullptr;
+        // without the Eq. 15 norms the adjoint writes the gradient step eta_hat - g_hat / L
+        // and the update pass reads it in place of g_hat and eta_hat (as a single scan does)
+        f.fs.pre = !norms && p->ny == 1;
         b->nurec[NK_FWD_FISTA].host[i].a.stop = norms ? &b->stops[i].iter : nullptr;
-        b->nurec[NK_ADJ_FISTA].host[i].a.stop = norms ? &b->stops[i].iter : nullptr;
+        isam::NufftArgs& aa = b->nurec[NK_ADJ_FISTA].host[i].a;
+        aa.stop = norms ? &b->stops[i].iter : nullptr;
+        aa.step_eta = f.fs.pre ? p->fista_hat : nullptr;
+        aa.gstep = f.fs.step;
     }
     int rc = b->latrec[LK_FISTA].upload(s);
     rc = rc ? rc : b->nurec[NK_FWD_FISTA].upload(s);
