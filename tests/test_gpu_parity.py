@@ -380,6 +380,28 @@ def test_fista_wide_lateral_tiles(P, nx):
     assert abs(res.resid2 - ref.resid2[-1]) < 1e-4 * ref.resid2[-1]
 
 
+def test_fista_gradient_step_forms_agree(P):
+    """Without a tolerance the adjoint writes the gradient step eta_hat - g_hat / L itself;
+    with one (here one that never holds) it writes g_hat and the update pass forms the
+    step.  Both must give the same iterates up to FP32 rounding, on a B-scan with a
+    fractional focal row and on one whose depth FFT is K = 4096 (whose adjoint fetches its
+    epilogue operands ahead)."""
+    for nx, nk, focus in ((256, 512, 37.5), (64, 2048, 512)):
+        o = ph.custom_optics(nx, nk, edge_phase2=30 * math.pi, edge_phase3=6 * math.pi, focus_rows=focus)
+        rng = np.random.default_rng(nx + nk)
+        eta = ph.layers(rng, nx, nk, 2) + ph.point_scatterers(rng, nx, nk, nx // 4)
+        y = ph.add_noise(O.Operator(O.Geometry.of(o), "N").A(eta), 25.0, nk)
+        with make_plan(P, o) as plan:
+            L = plan.lipschitz(iters=50, seed=0)
+            lam = 0.05 * plan.lambda_max(to_dev(y))
+            a = plan.fista(to_dev(y), lam, 60, L=L)
+            b = plan.fista(to_dev(y), lam, 60, tol=1e-30, L=L)
+            za, zb = to_host(a.eta), to_host(b.eta)
+        assert a.iters == b.iters == 60
+        assert rel(za, zb) < 2e-6, (nx, nk)
+        assert abs(a.resid2 - b.resid2) < 1e-5 * b.resid2
+
+
 def test_fista_tiny_weighted_stop_and_residual(P):
     """Depth weights (MBIR+), the Eq. 15 stop and the residual add-back of Alg. 1.
 
