@@ -34,11 +34,15 @@ reading it takes; each function names the passage it follows.
 from __future__ import annotations
 
 import math
+import os
+from concurrent.futures import ProcessPoolExecutor
 from dataclasses import dataclass, fields
+import multiprocessing
 
 import numpy as np
 import scipy.linalg
 import scipy.sparse
+from threadpoolctl import threadpool_limits
 
 __all__ = [
     "Geometry", "grids", "beam_filter", "dispersion_phase", "axial_wavenumber",
@@ -46,7 +50,7 @@ __all__ = [
     "minmax_error", "forward", "adjoint", "forward_exact", "adjoint_exact",
     "forward_nufft", "adjoint_nufft", "soft_threshold", "lipschitz", "lambda_max",
     "fista", "dense_matrix", "Operator", "resampled_spectrum", "calibration_derivatives",
-    "calibration_gradient", "volume_q2", "VolumeOperator",
+    "calibration_gradient", "volume_q2", "VolumeOperator", "direct_image", "default_workers",
 ]
 
 
@@ -368,16 +372,64 @@ def adjoint_nufft(g: Geometry, r: np.ndarray, columns=None, P=None) -> np.ndarra
     return _lateral_ifft(eta_hat)
 
 
-class Operator:
-    """A = Re o K^ and A^H with cached interpolation matrices (mode N) for repeated use."""
+def default_workers() -> int:
+    """Worker processes for building interpolation matrices: the CPUs this process may use, at most 16."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:          # pragma: no cover - platforms without affinity
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
 
-    def __init__(self, g: Geometry, mode: str = "N"):
+
+def _interp_chunk(g: Geometry, q2, cols):
+    """Interpolation matrices of the given columns (a unit of work for a worker process).
+
+    q2 None: the B-scan columns l of g (stolt_points); otherwise the per-column lateral
+    frequencies of a volume (_column_model).  Same arithmetic as a serial build.
+    """
+    # the small dense products of the per-point least squares run fastest on one BLAS thread
+    # (and then round alike in every process)
+    with threadpool_limits(limits=1):
+        if q2 is None:
+            tables = stolt_points(g)
+        else:
+            tables = _column_model(g, q2)[2]
+        return [_interp_matrix(g, l, None, tables) for l in cols]
+
+
+def _interp_matrices(g: Geometry, ncols: int, q2=None, workers: int = 1) -> list:
+    """P_l for l < ncols, built serially or split over `workers` spawned processes.
+
+    Only the order of construction changes with `workers`; every matrix is produced by
+    _interp_matrix from the same tables, so the result is identical.
+    """
+    if workers <= 1 or ncols < 2 * workers:
+        return _interp_chunk(g, q2, range(ncols))
+    chunks = [list(range(ncols))[i::workers] for i in range(workers)]
+    ctx = multiprocessing.get_context("spawn")
+    with ProcessPoolExecutor(max_workers=workers, mp_context=ctx) as ex:
+        parts = list(ex.map(_interp_chunk, [g] * workers, [q2] * workers, chunks))
+    out = [None] * ncols
+    for ch, mats in zip(chunks, parts):
+        for l, m in zip(ch, mats):
+            out[l] = m
+    return out
+
+
+class Operator:
+    """A = Re o K^ and A^H with cached interpolation matrices (mode N) for repeated use.
+
+    ``workers`` > 1 builds the matrices in that many processes (large grids only; the
+    matrices, and hence every result, are the same as with one).
+    """
+
+    def __init__(self, g: Geometry, mode: str = "N", workers: int = 1):
         self.g = g
         self.mode = mode
         self.P = None
         if mode == "N":
-            tables = stolt_points(g)
-            self.P = {l: _interp_matrix(g, l, None, tables) for l in range(g.nx)}
+            mats = _interp_matrices(g, g.nx, None, workers)
+            self.P = {l: mats[l] for l in range(g.nx)}
         elif mode != "E":
             raise ValueError(mode)
 
@@ -461,7 +513,7 @@ class VolumeOperator:
     modulation with q^2 = qx^2 + qy^2.
     """
 
-    def __init__(self, g: Geometry, mode: str = "N"):
+    def __init__(self, g: Geometry, mode: str = "N", workers: int = 1):
         if mode not in ("E", "N"):
             raise ValueError(mode)
         self.g, self.mode = g, mode
@@ -469,7 +521,7 @@ class VolumeOperator:
         self.kz, self.c, tables = _column_model(g, self.q2)
         self.P = None
         if mode == "N":
-            self.P = [_interp_matrix(g, i, None, tables) for i in range(self.q2.size)]
+            self.P = _interp_matrices(g, self.q2.size, self.q2, workers)
 
     def _resample(self, eta_hat_cols):
         G = grids(self.g)
@@ -573,6 +625,27 @@ def calibration_gradient(g: Geometry, eta: np.ndarray, grad_s: np.ndarray, mode:
     cX = modulation(g) * X
     base = np.conj(Gs) * 1j * cX
     return np.array([float(np.sum(np.real(base * D))) for D in calibration_derivatives(g)])
+
+
+# --------------------------------------------------------------------------- baseline image
+
+def direct_image(g: Geometry, y: np.ndarray) -> np.ndarray:
+    """The "direct IFFT" image of Eq. 9 (Sec. "Methods under test"): dispersion compensation
+    e^{-j phi} on each measured A-scan, then the inverse transform along the spectral axis.
+
+    eta_d[p][m] = Nz^{-1/2} sum_n y[p][n] e^{-j phi(k_n)} e^{-2 j k_n z_m}, on the full-range
+    depth grid of the operator (rows m in [-Nz/2, Nz/2) at index m + Nz/2).  It is the adjoint
+    of the one-A-scan model with no lateral coupling (no Stolt map, beam filter or focus), so by
+    Eq. 9 it holds half the object plus the doubly dispersed conjugate mirror.  The kernel
+    e^{-2 j k_n z_m} is the one of the operator; a plain IFFT over the sample index differs from
+    it by a unimodular phase per depth row and by its normalisation.
+    Written as the direct sum (a dense matrix product), the definition.
+    """
+    G = grids(g)
+    y = np.asarray(y, np.float64)
+    Yd = y * np.exp(-1j * dispersion_phase(g))[None, :]
+    E = np.exp(-2j * np.outer(G.k, G.z))                     # (nk, nz)
+    return (Yd @ E) / math.sqrt(g.nk)
 
 
 # --------------------------------------------------------------------------- solver

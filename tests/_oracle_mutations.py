@@ -55,11 +55,39 @@ MUTATIONS = {
     # adjoint NUFFT with the interpolation matrix transposed but not conjugated
     "adjoint_nufft_no_conj": lambda: _patch("adjoint_nufft", _adjoint_nufft_no_conj),
     # FISTA momentum weight t_k / t_{k+1} instead of (t_k - 1) / t_{k+1}
-    "fista_momentum": lambda: _patch("fista", _fista_wrong_momentum),
+    "fista_momentum": lambda: _patch("fista", lambda *a, **k: _fista_momentum(lambda t, tn: t / tn, *a, **k)),
+    # the milder momentum slip (t_k - 1) / t_k, a convergent but different sequence
+    "fista_momentum_mild": lambda: _patch("fista", lambda *a, **k: _fista_momentum(lambda t, tn: (t - 1) / t, *a, **k)),
+    # beam filter of width w0^2 / 4 in the exponent instead of w0^2 / 8
+    "beam_width": lambda: _wrap("beam_filter", lambda f: lambda g: f(g) ** 2),
+    # dispersion polynomial expanded about k0 + dk instead of the centre wavenumber
+    "dispersion_k0_shift": lambda: _patch("dispersion_phase", _dispersion_k0_shift),
+    # direct image without the dispersion compensation (e^{+j phi})
+    "direct_no_compensation": lambda: _patch("direct_image", _direct_wrong_sign_phi),
+    # direct image with the conjugate depth kernel
+    "direct_kernel_conj": lambda: _patch("direct_image", _direct_conj_kernel),
 }
 
 
-def _fista_wrong_momentum(op, y, lam, L, iters, w=None, tol=0.0, add_residual=False, eps=1e-12, state=None):
+def _dispersion_k0_shift(g):
+    G = OI.grids(g)
+    d = G.k - (G.kc + G.dk)
+    return g.a2 * d ** 2 + g.a3 * d ** 3
+
+
+def _direct_wrong_sign_phi(g, y):
+    G = OI.grids(g)
+    Yd = np.asarray(y, np.float64) * np.exp(1j * OI.dispersion_phase(g))[None, :]
+    return (Yd @ np.exp(-2j * np.outer(G.k, G.z))) / math.sqrt(g.nk)
+
+
+def _direct_conj_kernel(g, y):
+    G = OI.grids(g)
+    Yd = np.asarray(y, np.float64) * np.exp(-1j * OI.dispersion_phase(g))[None, :]
+    return (Yd @ np.exp(2j * np.outer(G.k, G.z))) / math.sqrt(g.nk)
+
+
+def _fista_momentum(weight, op, y, lam, L, iters, w=None, tol=0.0, add_residual=False, eps=1e-12, state=None):
     y = np.asarray(y, np.float64)
     step = 1.0 / L
     w = np.ones(y.shape) if w is None else np.asarray(w, np.float64)
@@ -85,7 +113,7 @@ def _fista_wrong_momentum(op, y, lam, L, iters, w=None, tol=0.0, add_residual=Fa
         if tol > 0 and rr < tol:
             break
         t_next = (1 + math.sqrt(1 + 4 * t * t)) / 2
-        eta = z + (t / t_next) * (z - z_prev)
+        eta = z + weight(t, t_next) * (z - z_prev)
         z_prev = z
         t = t_next
     out = z

@@ -111,6 +111,45 @@ def test_mirror_symmetry(mode):
     assert rel(O.forward(g, mir, mode), O.forward(g, eta, mode)) > 0.1
 
 
+def test_beam_filter_is_the_two_way_gaussian_angular_spectrum():
+    """B(q) of Eq. 3 for a Gaussian beam of waist w0: the field at the focus is exp(-x^2/w0^2)
+    one way, exp(-2 x^2 / w0^2) for illumination times collection.  Its Fourier transform,
+    normalised at q = 0, is exp(-q^2 w0^2 / 8).  Here that transform is taken numerically: the
+    unitary DFT (numpy) of the sampled two-way field on a lateral grid much wider than the beam
+    and finely sampled (aliasing below e^-300), at the oracle's own lateral frequencies."""
+    w0 = 8e-6
+    g = O.Geometry(nx=512, nk=16, dx=0.5e-6, lambda_c=1300e-9, dlambda=170e-9, waist=w0,
+                   z_focus=0.0, a2=0.0, a3=0.0)
+    x = g.dx * np.fft.fftfreq(g.nx, d=1.0 / g.nx)             # periodic grid centred on x = 0
+    field2 = np.exp(-2 * x ** 2 / w0 ** 2)
+    F = np.fft.fft(field2)
+    want = np.real(F / F[0])
+    B = O.beam_filter(g)
+    assert np.all(B == B[:, :1])                               # no k dependence for a fixed waist
+    assert np.abs(B[:, 0] - want).max() < 1e-12
+    assert B[g.nx // 8, 0] < 0.5                               # the filter is not trivially flat here
+
+
+def test_dispersion_phase_at_band_centre_and_edges():
+    """Eq. 7 with k0 the centre wavenumber 2 pi / lambda_c: the workloads state dispersion as
+    the phase the quadratic (cubic) term reaches at the band edge |k - k0| = band / 2.  Sample 0
+    sits at k0 - band/2 and sample nk/2 at k0 (uniform sampling in k over the band), so
+    phi[0] = E2 - E3 and phi[nk/2] = 0, and the even and odd parts about the centre sample follow
+    the two edge phases at every offset."""
+    nk = 64
+    E2, E3 = 40 * math.pi, 8 * math.pi
+    g = O.Geometry.of(ph.custom_optics(8, nk, edge_phase2=E2, edge_phase3=E3))
+    phi = O.dispersion_phase(g)
+    assert abs(phi[0] - (E2 - E3)) < 1e-9
+    assert abs(phi[nk // 2]) < 1e-12
+    j = np.arange(1, nk // 2)
+    u = 2 * j / nk                                             # |k - k0| / (band / 2)
+    even = (phi[nk // 2 + j] + phi[nk // 2 - j]) / 2
+    odd = (phi[nk // 2 + j] - phi[nk // 2 - j]) / 2
+    assert np.abs(even - E2 * u ** 2).max() < 1e-9
+    assert np.abs(odd - E3 * u ** 3).max() < 1e-9
+
+
 # ------------------------------------------------------------------ adjoint
 
 @pytest.mark.parametrize("mode", ["E", "N"])
@@ -476,6 +515,27 @@ def test_fista_energy_of_beck_teboulle_is_nonincreasing():
     assert E[-1] < 0.5 * E[0]
 
 
+def test_fista_scalar_example_worked_by_hand():
+    """Alg. 1 on one complex unknown with A x = Re x, y = 1, L = 2 (step 1/2), lambda = 0.
+
+    From eta^1 = z^0 = 0, t^1 = 1: z^k = eta^k - (Re eta^k - 1)/2, t^{k+1} = (1 + sqrt(1 + 4 t_k^2))/2,
+    eta^{k+1} = z^k + ((t^k - 1)/t^{k+1})(z^k - z^{k-1}).  By hand: z^1 = 1/2; the first momentum
+    weight is 0, so z^2 = 3/4; t^2 = (1 + sqrt 5)/2, t^3 = (1 + sqrt(7 + 2 sqrt 5))/2, and
+    eta^3 = 3/4 + (t^2 - 1)/t^3 / 4, z^3 = 1/2 + eta^3 / 2 = 0.91021919...; then z^4.
+    The weights (t^k - 1)/t^k or t^k/t^{k+1} give 0.92274575... and 1.10144513... at k = 3."""
+    op = DenseOp(np.array([[1.0, 0.0]]), (1, 1))
+    y = np.array([[1.0]])
+    t2 = (1 + math.sqrt(5)) / 2
+    t3 = (1 + math.sqrt(7 + 2 * math.sqrt(5))) / 2
+    z3 = 0.5 + (0.75 + 0.25 * (t2 - 1) / t3) / 2
+    assert abs(z3 - 0.9102191906406651) < 1e-15
+    want = [0.5, 0.75, z3, 0.9898805870005736]
+    for k, zk in enumerate(want, start=1):
+        res = O.fista(op, y, lam=0.0, L=2.0, iters=k)
+        assert abs(res.z[0, 0] - zk) < 1e-14, k
+        assert res.z[0, 0].imag == 0.0
+
+
 def test_fista_relative_residual_stop_and_resume():
     g, op, y = _tiny_problem()
     lam = 0.1 * O.lambda_max(op, y)
@@ -494,6 +554,57 @@ def test_residual_add_back_is_one_gradient_step():
     plain = O.fista(op, y, lam, 1.0, iters=30)
     added = O.fista(op, y, lam, 1.0, iters=30, add_residual=True)
     assert rel(added.z, plain.z + op.AH(y - op.A(plain.z))) < 1e-14
+
+
+# ------------------------------------------------------------------ direct image (Eq. 9)
+
+def test_direct_image_is_the_per_ascan_in_focus_adjoint():
+    """With one A-scan only q = 0 exists (kz = 2k, no beam filter or focal term), so the
+    operator's adjoint is the dispersion-compensated transform of Eq. 9: the direct image of
+    every A-scan equals the one-A-scan adjoint of that A-scan, and A-scans do not mix."""
+    g = tiny_geom(6, 32, focus_rows=5)
+    rng = np.random.default_rng(31)
+    y = rng.standard_normal((g.nx, g.nk))
+    d = O.direct_image(g, y)
+    g1 = g.with_(nx=1)
+    for p in range(g.nx):
+        a = O.adjoint_exact(g1, y[p:p + 1])[0]
+        assert np.abs(d[p] - a).max() < 1e-12 * np.abs(a).max()
+
+
+def test_direct_image_against_numpy_fft():
+    """With k_c / dk = P an integer, e^{-2 i k_n z_m} = e^{-2 pi i (n + P - nk/2) m / nk}: the direct
+    image is numpy's forward FFT of y e^{-i phi} over the sample index, times a per-row phase."""
+    nk = 64
+    lam = 1300e-9
+    g = O.Geometry(nx=3, nk=nk, dx=4e-6, lambda_c=lam, dlambda=lam / 7.5, waist=8e-6,
+                   z_focus=0.0, a2=3e-10, a3=1e-16)
+    G = O.grids(g)
+    P = int(round(G.kc / G.dk))
+    assert abs(G.kc / G.dk - P) < 1e-6
+    rng = np.random.default_rng(32)
+    y = rng.standard_normal((g.nx, nk))
+    v = y * np.exp(-1j * O.dispersion_phase(g))[None, :]
+    m = np.arange(-nk // 2, nk // 2)
+    want = np.fft.fft(v, axis=1)[:, np.mod(m, nk)] * np.exp(-2j * math.pi * (P - nk // 2) * m / nk)[None, :]
+    want /= math.sqrt(nk)
+    got = O.direct_image(g, y)
+    assert np.abs(got - want).max() < 1e-11 * np.abs(want).max()
+
+
+def test_direct_image_holds_half_the_object_and_its_mirror():
+    """Eq. 9 with no dispersion: the real measurement carries the object and its conjugate
+    mirror with weight 1/2 each, and the direct image returns exactly that sum,
+    (eta + M eta) / 2 with (M eta)[m] = conj(eta[-m]) (row -nz/2 has no mirror)."""
+    nk = 32
+    g = tiny_geom(1, nk, edge_phase2=0.0, edge_phase3=0.0, focus_rows=0)
+    rng = np.random.default_rng(33)
+    eta = rand_obj(rng, 1, nk)
+    mir = np.zeros_like(eta)
+    mir[:, 1:] = np.conj(eta[:, :0:-1])
+    s = O.forward_exact(g, eta)
+    got = O.direct_image(g, s)
+    assert np.abs(got - (eta + mir) / 2).max() < 1e-12
 
 
 # ------------------------------------------------------------------ inputs
