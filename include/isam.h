@@ -57,8 +57,8 @@ enum {
     ISAM_EUNSUPPORTED = -3,  /* valid but not built: J != 6, osf != 2; nk not a power of two or
                                 above 4096; nx or ny not a built lateral length (powers of two up
                                 to 2048; 192, 320, 384, 448, 640, 768, 896, 1280, 1536, 1792);
-                                more than 2^30 object samples; a Stolt-mapped column spanning
-                                more than 5/4 of the oversampled depth period */
+                                more than 2^30 object samples; Stolt positions that break the
+                                adjoint's slot bounds (see isam_plan) */
     ISAM_ENOMEM = -4,        /* device allocation failed */
     ISAM_ENODEV = -5,        /* no HIP device visible */
     ISAM_EHIP = -6,          /* a HIP runtime call failed */
@@ -93,10 +93,17 @@ typedef struct {
     double L;                /* step constant used (1/L is the gradient step) */
 } isam_fista_info;
 
-/* Create a plan for geometry *g: validates, allocates tables and workspace, and
- * builds the tables in FP64 on the device (Stolt constants, beam filter,
- * dispersion and focus phases, Kaiser-Bessel scaling, the min-max weight
- * table, FFT twiddles).  Synchronises `stream` once at the end.
+/* Create a plan for geometry *g: the sampling of Sec. "Background" (N = nx ny nz,
+ * nz = nk), the Stolt map of Eq. 3 and the dispersion of Eq. 7, evaluated through the
+ * min-max NUFFT the paper adopts (Sec. "Efficient and robust ISAM through non-uniform
+ * FFT").  Validates, allocates tables and workspace, and builds the tables in FP64 on
+ * the device (Stolt constants, beam filter, dispersion and focus phases, Kaiser-Bessel
+ * scaling, the min-max weight table, FFT twiddles).  Then it checks on the device, with
+ * the kernels' own FP64 Stolt arithmetic, the two bounds that the adjoint's atomic-free
+ * transposed interpolation relies on (consecutive samples of a column at least two
+ * oversampled cells apart; a chunk of samples within its slot array); a geometry that
+ * breaks them gets EUNSUPPORTED.  At q = 0 the Stolt map is the identity and the
+ * positions advance by exactly two cells per sample.  Synchronises `stream`.
  * *out receives the plan (NULL on error).  Errors: EINVAL, EUNSUPPORTED,
  * ENODEV, ENOMEM, EHIP. */
 int isam_plan(const isam_geometry* g, void* stream, isam_plan_t* out);
@@ -163,6 +170,49 @@ int isam_fista(isam_plan_t p, const float* y, float lambda, const float* w, int 
                float tol, double L, int add_residual, void* eta_out, isam_fista_info* info,
                void* stream);
 
+/* Saved state of a FISTA solve (Alg. 1), for checkpoint and resume.  k: iterations done;
+ * t: the momentum sequence value t^{k+1} the next iteration uses; data: caller-owned device
+ * memory of isam_fista_state_bytes bytes holding the momentum point eta^{k+1} and the last
+ * iterate z^k in the plan's internal layout (opaque; valid only for a plan of the same
+ * geometry). */
+typedef struct {
+    int32_t k;
+    double t;
+    void* data;
+} isam_fista_state;
+
+/* Size in bytes of the device buffer of an isam_fista_state for plan p. */
+int isam_fista_state_bytes(isam_plan_t p, int64_t* bytes);
+
+/* isam_fista with checkpoint/resume and per-iteration records (Alg. 1, Eq. 15).
+ * resume: NULL (start at eta^1 = z^0 = 0, t^1 = 1) or a state saved by an earlier call on a
+ *   plan of the same geometry; iteration numbering continues at resume->k + 1, and running
+ *   a then b iterations gives bit for bit what a + b iterations give.
+ * save: NULL or a state whose data buffer receives the state after the last iteration run
+ *   (the stopping iteration if Eq. 15 stopped the solve); save->k and save->t are set.
+ *   save->data must not overlap y, w or eta_out; it may be resume->data.
+ * history: NULL or host double[max_iter][3]; row i receives, for iteration i + 1 of this
+ *   call, r_r of Eq. 15, ||A eta^k - y||^2 at the momentum point and sum_i w_i |z^k_i|
+ *   (rows past info->iters_run are not written).  Forming them costs the Eq. 15 norms on
+ *   every iteration.
+ * Other arguments, results and errors as isam_fista; eta_out is unspecified when the
+ * status is ENONFINITE. */
+int isam_fista_ex(isam_plan_t p, const float* y, float lambda, const float* w, int max_iter,
+                  float tol, double L, int add_residual, const isam_fista_state* resume,
+                  isam_fista_state* save, double* history, void* eta_out, isam_fista_info* info,
+                  void* stream);
+
+/* The "direct IFFT" image of Eq. 9 (Sec. "Methods under test"), the reference the paper
+ * compares MBIR with: each measured A-scan is dispersion-compensated by e^{-j phi(k)} and
+ * transformed along k onto the full-range depth grid,
+ *   eta_out[p][m + nk/2] = nk^{-1/2} sum_n y[p][n] e^{-j phi(k_n)} e^{-2 j k_n z_m},
+ * with the operator's depth kernel (a plain inverse FFT over the sample index differs by a
+ * unimodular phase per depth row and its scaling).  It holds half the object plus the
+ * doubly dispersed conjugate mirror; A-scans are independent (no Stolt map, beam filter or
+ * focus).  y: device float32 [nx][nk]; eta_out: device complex64 [nx][nk]; must not alias.
+ * One nk-point LDS FFT per A-scan.  Errors: EINVAL (NULL), EALIAS. */
+int isam_direct(isam_plan_t p, const float* y, void* eta_out, void* stream);
+
 /* Per-pass timing (profiling support).  enable = 1 clears the accumulators and
  * makes every later operator / FISTA call on the plan attach a HIP event pair
  * to each pass's kernel launch on its stream (the runtime stamps the pair with
@@ -175,8 +225,9 @@ int isam_fista(isam_plan_t p, const float* y, float lambda, const float* w, int 
  *   3 lateral R2C                    4 Stolt NUFFT adjoint
  *   5 lateral FFT (inverse)          6 FISTA update pass
  *   7 y transform of a volume (both directions; x passes count under 0, 2, 3, 5)
+ *   8 direct image (isam_direct)
  * Synchronises the plan's last stream before reading. */
-#define ISAM_NPASS 8
+#define ISAM_NPASS 9
 int isam_timing(isam_plan_t p, int enable, double* ms_out, int64_t* count_out);
 
 /* ------------------------------------------------------------------------

@@ -40,6 +40,7 @@ from dataclasses import dataclass, fields
 import multiprocessing
 
 import numpy as np
+import scipy.fft
 import scipy.linalg
 import scipy.sparse
 from threadpoolctl import threadpool_limits
@@ -51,7 +52,18 @@ __all__ = [
     "forward_nufft", "adjoint_nufft", "soft_threshold", "lipschitz", "lambda_max",
     "fista", "dense_matrix", "Operator", "resampled_spectrum", "calibration_derivatives",
     "calibration_gradient", "volume_q2", "VolumeOperator", "direct_image", "default_workers",
+    "set_fft_workers",
 ]
+
+# Threads of the library FFTs (scipy.fft's `workers`); 1 unless a caller asks for more.
+_FFT_WORKERS = 1
+
+
+def set_fft_workers(n: int) -> int:
+    """Set the thread count of the oracle's FFTs; returns the previous value."""
+    global _FFT_WORKERS
+    prev, _FFT_WORKERS = _FFT_WORKERS, max(1, int(n))
+    return prev
 
 
 # --------------------------------------------------------------------------- geometry
@@ -175,11 +187,11 @@ def modulation(g: Geometry) -> np.ndarray:
 
 def _lateral_fft(x):
     """Unitary lateral DFT, exp(-2 pi i l p / Nx) / sqrt(Nx) (the F_<-> of Eq. 2)."""
-    return np.fft.fft(x, axis=0, norm="ortho")
+    return scipy.fft.fft(x, axis=0, norm="ortho", workers=_FFT_WORKERS)
 
 
 def _lateral_ifft(x):
-    return np.fft.ifft(x, axis=0, norm="ortho")
+    return scipy.fft.ifft(x, axis=0, norm="ortho", workers=_FFT_WORKERS)
 
 
 # --------------------------------------------------------------------------- mode E
@@ -298,7 +310,7 @@ def _oversampled_spectrum(g: Geometry, eta_hat_rows: np.ndarray) -> np.ndarray:
     rows = np.atleast_2d(eta_hat_rows)
     buf = np.zeros((rows.shape[0], G.K), np.complex128)
     buf[:, np.mod(G.m, G.K)] = rows * s[None, :]
-    return G.K * np.fft.ifft(buf, axis=1)
+    return G.K * scipy.fft.ifft(buf, axis=1, workers=_FFT_WORKERS)
 
 
 def _interp_matrix(g: Geometry, l: int, rows=None, tables=None) -> scipy.sparse.csr_matrix:
@@ -367,7 +379,7 @@ def adjoint_nufft(g: Geometry, r: np.ndarray, columns=None, P=None) -> np.ndarra
     for l in cols:
         Pl = P[l] if P is not None else _interp_matrix(g, l, None, tables)
         Yp = Pl.conj().T @ Xp[l]
-        full = np.fft.fft(Yp)                       # sum_g Y'[g] exp(-2 pi i g m / K) at index m mod K
+        full = scipy.fft.fft(Yp)                     # sum_g Y'[g] exp(-2 pi i g m / K) at index m mod K
         eta_hat[l] = s * full[np.mod(G.m, G.K)] / math.sqrt(g.nk)
     return _lateral_ifft(eta_hat)
 
@@ -535,14 +547,17 @@ class VolumeOperator:
 
     def A(self, eta):
         g = self.g
-        eta_hat = np.fft.fft2(np.asarray(eta, np.complex128), axes=(0, 1), norm="ortho")
+        eta_hat = scipy.fft.fft2(np.asarray(eta, np.complex128), axes=(0, 1), norm="ortho",
+                                 workers=_FFT_WORKERS)
         X = self._resample(eta_hat.reshape(g.ny * g.nx, g.nk))
-        return np.real(np.fft.ifft2((self.c * X).reshape(g.ny, g.nx, g.nk), axes=(0, 1), norm="ortho"))
+        return np.real(scipy.fft.ifft2((self.c * X).reshape(g.ny, g.nx, g.nk), axes=(0, 1), norm="ortho",
+                                       workers=_FFT_WORKERS))
 
     def AH(self, r):
         g = self.g
         G = grids(g)
-        R = np.fft.fft2(np.asarray(r, np.float64).astype(np.complex128), axes=(0, 1), norm="ortho")
+        R = scipy.fft.fft2(np.asarray(r, np.float64).astype(np.complex128), axes=(0, 1), norm="ortho",
+                           workers=_FFT_WORKERS)
         Xp = np.conj(self.c) * R.reshape(g.ny * g.nx, g.nk)
         s = kb_scaling(g)
         out = np.empty_like(Xp)
@@ -550,10 +565,11 @@ class VolumeOperator:
             if self.mode == "E":
                 out[i] = np.conj(np.exp(1j * self.kz[i][:, None] * G.z[None, :])).T @ Xp[i]
             else:
-                full = np.fft.fft(self.P[i].conj().T @ Xp[i])
+                full = scipy.fft.fft(self.P[i].conj().T @ Xp[i])
                 out[i] = s * full[np.mod(G.m, G.K)]
         out /= math.sqrt(g.nk)
-        return np.fft.ifft2(out.reshape(g.ny, g.nx, g.nk), axes=(0, 1), norm="ortho")
+        return scipy.fft.ifft2(out.reshape(g.ny, g.nx, g.nk), axes=(0, 1), norm="ortho",
+                               workers=_FFT_WORKERS)
 
     def calibration_gradient(self, eta, grad_s) -> np.ndarray:
         """Gradient of <grad_s, A eta> with respect to (a2, a3, z_focus) for a volume.
@@ -563,9 +579,11 @@ class VolumeOperator:
         """
         g = self.g
         G = grids(g)
-        eta_hat = np.fft.fft2(np.asarray(eta, np.complex128), axes=(0, 1), norm="ortho")
+        eta_hat = scipy.fft.fft2(np.asarray(eta, np.complex128), axes=(0, 1), norm="ortho",
+                                 workers=_FFT_WORKERS)
         X = self._resample(eta_hat.reshape(g.ny * g.nx, g.nk))
-        Gs = np.fft.fft2(np.asarray(grad_s, np.float64).astype(np.complex128), axes=(0, 1), norm="ortho")
+        Gs = scipy.fft.fft2(np.asarray(grad_s, np.float64).astype(np.complex128), axes=(0, 1), norm="ortho",
+                            workers=_FFT_WORKERS)
         base = np.conj(Gs.reshape(g.ny * g.nx, g.nk)) * 1j * self.c * X
         d = (G.k - G.kc)[None, :]
         derivs = (np.broadcast_to(d ** 2, base.shape), np.broadcast_to(d ** 3, base.shape), 2 * G.k[None, :] - self.kz)

@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libisam.so")
-SOURCES = ["tables.hip", "lateral.hip", "lateral_real.hip", "lateral_fista.hip", "nufft.hip", "solver.hip", "batch.hip"]
+SOURCES = ["tables.hip", "lateral.hip", "lateral_real.hip", "lateral_fista.hip", "nufft.hip", "solver.hip", "batch.hip", "direct.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -92,3 +92,27 @@ ISAM_DEV int xcd_tile(int b, int nblocks) {
     const int per = nblocks / NXCD;
     return (b % NXCD) * per + b / NXCD;
 }
+
+// Tables of the direct image (Eq. 9) at index i < nk: D = e^{-j phi(k_i)} with
+// phi = a2 d^2 + a3 d^3, d = (i - nk/2) dk (Eq. 7), and for row m = i - nk/2 the phase
+// P = e^{-2 j kc dz m} (-1)^m / sqrt(nk) that turns an FFT over the sample index into the sum
+// over e^{-2 j k_n z_m}.  FP64, arguments reduced mod 2 pi; no contraction, so every kernel
+// that calls this stores the same bits.
+ISAM_DEV void direct_table_entry(int i, int nk, double kc, double dk, double dz, double a2, double a3,
+                                 float2& D, float2& P) {
+#pragma clang fp contract(off)
+    constexpr double kTwoPi = 6.283185307179586476925286766559;
+    const double d = (i - nk / 2) * dk;
+    double phi = a2 * d * d + a3 * d * d * d;
+    phi -= kTwoPi * rint(phi / kTwoPi);
+    double sn, cs;
+    sincos(-phi, &sn, &cs);
+    D = make_float2((float)cs, (float)sn);
+    const int m = i - nk / 2;
+    double th = 2.0 * kc * dz * m;
+    th -= kTwoPi * rint(th / kTwoPi);
+    sincos(-th, &sn, &cs);
+    const double norm = 1.0 / sqrt((double)nk);
+    const double sg = (m & 1) ? -norm : norm;
+    P = make_float2((float)(cs * sg), (float)(sn * sg));
+}

@@ -69,7 +69,7 @@ constexpr bool fft_length_ok(int N, int L = 4) {
 
 // Entry e of the staged table of a length-N transform: (exponent, period) of the
 // twiddle exp(-2 pi i exponent / period) it holds.
-inline void fft_stage_entry(int N, int L, int e, int& expo, int& period) {
+__host__ __device__ inline void fft_stage_entry(int N, int L, int e, int& expo, int& period) {
     const int np = fft_np(N, L);
     for (int p = 1; p < np; ++p) {
         const int R = fft_radix(N, p, L), NS = fft_stride(N, p, L);

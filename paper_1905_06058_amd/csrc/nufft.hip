@@ -82,8 +82,21 @@ struct NuAdjCfg {
 
 // Stolt grid position of sample n of a column with q^2 = q2 (FP64).  Returns false on an
 // evanescent sample (4 k^2 <= q^2).  t = kz dz K / (2 pi); fl = floor(t); tau = t - fl.
+// At q = 0 the Stolt map is the identity (kz = 2k) and t advances by exactly osf = K / nk per
+// sample: t = t0 + 2 (n - nk/2) with floor(t0) and t0 - floor(t0) decided once on the host, so
+// consecutive samples sit exactly two cells apart whatever the rounding of t0.  Elsewhere
+// kz is the FP64 square root below.  Every operation is spelled out (explicit fused
+// multiply-adds, no contraction), so each kernel that inlines this, and the plan-time check of
+// the adjoint's slot bounds (k_nufft_check), computes bit-identical positions.
 ISAM_DEV bool stolt_point(const NufftArgs& a, double q2, int n, double& t, int& fl, float& tau) {
-    const double k = a.kc + (double)(n - a.nk / 2) * a.dk;
+#pragma clang fp contract(off)
+    if (q2 == 0.0) {
+        fl = a.f0 + 2 * (n - a.nk / 2);
+        tau = a.tau0;
+        t = a.t0 + 2.0 * (n - a.nk / 2);
+        return true;
+    }
+    const double k = fma((double)(n - a.nk / 2), a.dk, a.kc);
     const double tk = 2.0 * k;
     const double d = fma(tk, tk, -q2);
     if (!(d > 0.0)) return false;
@@ -736,47 +749,50 @@ hipError_t nufft_adj_batch(int K_, const NuScan* recs, const int2* map, int nblk
     });
 }
 
-// Host replica of the Stolt positions per column.  Two bounds keep the adjoint exact:
-// (1) consecutive propagating samples advance by at least 2 cells (dkz/dk >= 2 holds for
-// any propagating component), so no two samples share a slot of a cell; (2) the cells of a
-// chunk of samples, [g0_first + 1, g0_last + J], fit the chunk's slot array.  A margin of
-// a few cells covers FP64 rounding differences between host and device at floor boundaries.
 int nufft_fwd_blocks(const isam_plan_s* p) { return p->npairs; }
 int nufft_adj_blocks(const isam_plan_s* p) { return p->npairs; }
 
-int nufft_span_ok(const isam_plan_s* p) {
-    int cs = 64;
-    int slotc = 0;
-    ISAM_K_SWITCH_INT(p->K, cs = NuAdjCfg<K>::CS; slotc = NuAdjCfg<K>::SLOTC);
-    // q^2 depends on |lx| and |ly| only
-    const double kPiH = 3.14159265358979323846;
-    for (int i = 0; i < (p->nx / 2 + 1) * (p->ny / 2 + 1); ++i) {
-        const int l = i / (p->ny / 2 + 1), m = i % (p->ny / 2 + 1);
-        const double qx = 2.0 * kPiH * l / (p->nx * p->g.dx);
-        const double qy = p->ny > 1 ? 2.0 * kPiH * m / (p->ny * p->g.dy) : 0.0;
-        const double q2 = qx * qx + qy * qy;
-        auto g0 = [&](int n, bool& prop) {
-            const double k = p->kc + (double)(n - p->nk / 2) * p->dk;
-            const double d = 4.0 * k * k - q2;
-            prop = d > 0.0;
-            return prop ? std::floor(std::sqrt(d) * p->cT) - kJ / 2 : 0.0;
-        };
-        for (int c0 = 0; c0 < p->nk; c0 += cs) {
-            double first = 0, last = 0, prev = 0;
-            bool have = false;
-            for (int n = c0; n < c0 + cs && n < p->nk; ++n) {
-                bool prop;
-                const double g = g0(n, prop);
-                if (!prop) continue;
-                if (have && g - prev < 2.0) return 0;
-                if (!have) first = g;
-                have = true;
-                prev = last = g;
-            }
-            if (have && last - first + kJ + 4 > slotc) return 0;
-        }
+namespace {
+
+// The adjoint's transposed interpolation gives every (cell, slot) of a chunk one writer.  That
+// holds if (1) consecutive propagating samples of a chunk have floor(t) at least 2 apart
+// (dkz/dk >= 2 for any propagating component, exactly 2 at q = 0), and (2) the cells of a
+// chunk, [g0_first + 1, g0_last + J], fit its slot array.  One thread per (column, chunk)
+// walks the chunk's samples with stolt_point itself, so the check sees exactly the positions
+// the kernels compute, and writes 1 into partials[col][chunk] if either bound fails, else 0.
+template <int K>
+__global__ __launch_bounds__(256) void k_nufft_check(NufftArgs a, float* __restrict__ partials) {
+    using Cf = NuAdjCfg<K>;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= a.ncol * Cf::NCH) return;
+    const int col = i / Cf::NCH, ch = i % Cf::NCH;
+    const double q2 = a.q2[col];
+    int first = 0, prev = 0;
+    bool have = false, bad = false;
+    for (int n = ch * Cf::CS; n < (ch + 1) * Cf::CS && n < a.nk; ++n) {
+        double t;
+        int fl;
+        float tau;
+        if (!stolt_point(a, q2, n, t, fl, tau)) continue;
+        if (have && fl - prev < 2) bad = true;
+        if (!have) first = fl;
+        have = true;
+        prev = fl;
     }
-    return 1;
+    if (have && prev - first + kJ > Cf::SLOTC) bad = true;
+    partials[col * kRedSlots + ch] = bad ? 1.f : 0.f;
+}
+
+}  // namespace
+
+hipError_t nufft_check(const isam_plan_s* p, float* partials, int* nslots, hipStream_t s) {
+    ISAM_K_SWITCH(p->K, {
+        const int n = p->ncol * NuAdjCfg<K>::NCH;
+        *nslots = NuAdjCfg<K>::NCH;
+        static_assert(NuAdjCfg<K>::NCH <= kRedSlots, "one flag per chunk in a partials row");
+        hipLaunchKernelGGL(k_nufft_check<K>, dim3((n + 255) / 256), dim3(256), 0, s, p->nufft_args(), partials);
+        return hipGetLastError();
+    });
 }
 
 }  // namespace isam

@@ -48,6 +48,10 @@ struct NufftArgs {
     double mr_over_K;       // fractional focal row / K (per-point phase exp(-2 pi i m_r t / K))
     double kc, dk;          // k_n = kc + (n - nk/2) dk
     double cT;              // Stolt grid position t = kz * cT, cT = dz K / (2 pi)
+    // q = 0 (kz = 2k): t_n = t0 + osf (n - nk/2) exactly, split once into floor(t0) and t0 - floor(t0)
+    int f0;
+    float tau0;
+    double t0;
     const double* q2;       // [nx] q_l^2 (FP64)
     const float* Bl;        // [nx] beam filter exp(-q^2 w0^2 / 8)
     const float2* En;       // [nk] e^{i phi(k_n)} e^{2 i k_n z_f} / sqrt(nz)
@@ -129,6 +133,8 @@ struct isam_plan_s {
     double kc, band, dk, dz, cT, beta, mf;
     int mi;
     double mr;
+    double t0;                    // Stolt position 2 kc cT of the centre sample at q = 0
+    int f0;                       // floor(t0)
     int lat_c = 0;                // lateral tile width of complex passes (lanes); 0 = default
     int lat_cr = 0;               // lateral tile width of real passes (lanes); 0 = default
     int lat_cy = 0;               // tile width of the y transform of a volume (lanes); 0 = default
@@ -142,6 +148,9 @@ struct isam_plan_s {
     float2* twK = nullptr;
     float2* twK8 = nullptr;
     float2* twX[5] = {};          // staged lateral twiddles for radix caps 2^2, 2^3, 2^4 (index = log2 cap)
+    float2* twN = nullptr;        // staged twiddles of the nk-point FFT (direct image), radices up to 16
+    float2* Dn = nullptr;         // [nk] e^{-i phi(k_n)} (dispersion compensation of the direct image)
+    float2* Pm = nullptr;         // [nk] per-row phase of the direct image, divided by sqrt(nk)
     float2* twY[5] = {};          // the same for the y transform of a volume
     isam::FwdPair* pairs = nullptr;   // [npairs] NUFFT column pairs
     double* wscratch = nullptr;   // FP64 scratch of the weight-table build
@@ -164,6 +173,8 @@ struct isam_plan_s {
     double* host_sums = nullptr;  // pinned host copy of red.sums
     isam::StopState* stop = nullptr;       // device stop-rule state of the solver
     isam::StopState* host_stop = nullptr;  // pinned host copy
+    double* hist = nullptr;       // per-iteration FISTA history [cap][3] (device), grown on demand
+    int hist_cap = 0;
 
     // per-pass timing (isam_timing)
     int timing_on = 0;
@@ -221,6 +232,10 @@ hipError_t nufft_adj(const isam_plan_s* p, const float2* rh, float2* ghat, hipSt
                      const int* stop = nullptr, const float2* step_eta = nullptr, float gstep = 0.f);
 hipError_t nufft_calgrad(const isam_plan_s* p, const float2* etahat, const float2* ghalf, float* partials,
                          hipStream_t s);
-int nufft_span_ok(const isam_plan_s* p);          // host check of the Stolt span bound
+// Device check, with the kernels' own Stolt arithmetic, of the two bounds the adjoint's
+// single-writer slots rely on; writes one flag per (column, chunk) into partials.
+hipError_t nufft_check(const isam_plan_s* p, float* partials, int* nslots, hipStream_t s);
+// Direct image of Eq. 9 (per A-scan dispersion compensation and inverse transform).
+hipError_t direct_image(const isam_plan_s* p, const float* y, float2* out, hipStream_t s);
 
 }  // namespace isam

@@ -22,8 +22,13 @@ using namespace isam;
 
 namespace {
 
+// Maximum that keeps a NaN (fmax would drop it), so that a non-finite input reaches the host.
+ISAM_DEV double nan_max(double a, double b) { return a != a ? a : (b != b ? b : fmax(a, b)); }
+ISAM_DEV float nan_maxf(float a, float b) { return a != a ? a : (b != b ? b : fmaxf(a, b)); }
+
 // FP64 sums (or maxima) of the per-workgroup partials: strided per-thread sums, then a
 // fixed-order tree, so the result does not depend on scheduling.
+
 __global__ __launch_bounds__(256) void k_finalize(const float* __restrict__ partials, int nblocks,
                                                   int nslots, double* __restrict__ sums, int mode_max) {
     __shared__ double sh[256];
@@ -32,12 +37,12 @@ __global__ __launch_bounds__(256) void k_finalize(const float* __restrict__ part
         double acc = 0.0;
         for (int b = tid; b < nblocks; b += 256) {
             const double v = partials[b * kRedSlots + s];
-            acc = mode_max ? fmax(acc, v) : acc + v;
+            acc = mode_max ? nan_max(acc, v) : acc + v;
         }
         sh[tid] = acc;
         __syncthreads();
         for (int w = 128; w > 0; w >>= 1) {
-            if (tid < w) sh[tid] = mode_max ? fmax(sh[tid], sh[tid + w]) : sh[tid] + sh[tid + w];
+            if (tid < w) sh[tid] = mode_max ? nan_max(sh[tid], sh[tid + w]) : sh[tid] + sh[tid + w];
             __syncthreads();
         }
         if (tid == 0) sums[s] = sh[0];
@@ -45,34 +50,44 @@ __global__ __launch_bounds__(256) void k_finalize(const float* __restrict__ part
     }
 }
 
-// Relative-residual stop rule (Eq. 15) on the device.  Sums slots 0..2 of the update
-// pass's partials (||z - eta||^2, ||g||^2, ||z - eta + g||^2) in FP64 with a fixed-order
-// tree, forms r_r and records iteration k in st->iter once r_r < tol (or the status on a
-// non-finite norm).  Does nothing once a stop has been recorded.
-__global__ __launch_bounds__(256) void k_stop_check(const float* __restrict__ partials, int nblocks,
-                                                    isam::StopState* st, int k, float tol) {
+// Per-iteration record of the solve on the device (Eq. 15).  Sums slots 0..3 of the update
+// pass's partials (||z - eta||^2, ||g||^2, ||z - eta + g||^2, sum w|z|) and slot 0 of the
+// forward NUFFT's (||A eta - y||^2) in FP64 with a fixed-order tree and forms r_r.  With
+// tol > 0 it records iteration k in st->iter once r_r < tol; a non-finite norm records k and
+// the status ENONFINITE (so the solver kernels stop).  With hist, row `row` of hist receives
+// (r_r, ||A eta^k - y||^2, sum w|z^k|).  Does nothing once a stop has been recorded.
+__global__ __launch_bounds__(256) void k_stop_check(const float* __restrict__ part_f, int nf,
+                                                    const float* __restrict__ part_r, int nr,
+                                                    isam::StopState* st, int k, float tol,
+                                                    double* __restrict__ hist, int row) {
     if (st->iter) return;                              // uniform
-    __shared__ double sh[3][256];
+    __shared__ double sh[5][256];
     const int tid = threadIdx.x;
-    double acc[3] = {0.0, 0.0, 0.0};
-    for (int b = tid; b < nblocks; b += 256)
-        for (int i = 0; i < 3; ++i) acc[i] += partials[b * kRedSlots + i];
-    for (int i = 0; i < 3; ++i) sh[i][tid] = acc[i];
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int b = tid; b < nf; b += 256)
+        for (int i = 0; i < 4; ++i) acc[i] += part_f[b * kRedSlots + i];
+    for (int b = tid; b < nr; b += 256) acc[4] += part_r[b * kRedSlots];
+    for (int i = 0; i < 5; ++i) sh[i][tid] = acc[i];
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (tid < w)
-            for (int i = 0; i < 3; ++i) sh[i][tid] += sh[i][tid + w];
+            for (int i = 0; i < 5; ++i) sh[i][tid] += sh[i][tid + w];
         __syncthreads();
     }
     if (tid == 0) {
-        const double d = sh[0][0], g = sh[1][0], e = sh[2][0];
-        if (!isfinite(d) || !isfinite(g) || !isfinite(e)) {
+        const double d = sh[0][0], g = sh[1][0], e = sh[2][0], l1 = sh[3][0], r2 = sh[4][0];
+        const double rr = sqrt(d) / (fmax(sqrt(g), sqrt(e)) + 1e-12);
+        if (hist) {
+            hist[3 * row] = rr;
+            hist[3 * row + 1] = r2;
+            hist[3 * row + 2] = l1;
+        }
+        if (!isfinite(d) || !isfinite(g) || !isfinite(e) || !isfinite(l1) || !isfinite(r2)) {
             st->status = ISAM_ENONFINITE;
             st->iter = k;
         } else {
-            const double rr = sqrt(d) / (fmax(sqrt(g), sqrt(e)) + 1e-12);
             st->rel_res = rr;
-            if (rr < (double)tol) st->iter = k;
+            if (tol > 0.f && rr < (double)tol) st->iter = k;
         }
     }
 }
@@ -103,14 +118,15 @@ __global__ __launch_bounds__(256) void k_absmax(const float2* __restrict__ x, co
     for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
         float v = sqrtf(cabs2(x[i]));
         if (w) v /= w[i];
-        m = fmaxf(m, v);
+        m = nan_maxf(m, v);
     }
-    m = wave_max(m);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = nan_maxf(m, __shfl_xor(m, off, 64));
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     if (lane == 0) scratch[wid] = m;
     __syncthreads();
     if (threadIdx.x == 0)
-        partials[blockIdx.x * kRedSlots] = fmaxf(fmaxf(scratch[0], scratch[1]), fmaxf(scratch[2], scratch[3]));
+        partials[blockIdx.x * kRedSlots] = nan_maxf(nan_maxf(scratch[0], scratch[1]), nan_maxf(scratch[2], scratch[3]));
 }
 
 // x *= 1 / sqrt(sums[slot])
@@ -445,22 +461,50 @@ int fista_finish(isam_plan_t p, double L, int add_residual, float2* out, hipStre
 
 }  // namespace isam
 
-extern "C" int isam_fista(isam_plan_t p, const float* y, float lambda, const float* w, int max_iter,
-                          float tol, double L, int add_residual, void* eta_out, isam_fista_info* info,
-                          void* stream) {
+extern "C" int isam_fista_state_bytes(isam_plan_t p, int64_t* bytes) {
+    if (!p || !bytes) return ISAM_EINVAL;
+    *bytes = (int64_t)2 * p->ncol * p->nk * (int64_t)sizeof(float2);
+    return ISAM_OK;
+}
+
+extern "C" int isam_fista_ex(isam_plan_t p, const float* y, float lambda, const float* w, int max_iter,
+                             float tol, double L, int add_residual, const isam_fista_state* resume,
+                             isam_fista_state* save, double* history, void* eta_out, isam_fista_info* info,
+                             void* stream) {
     if (!p || !y || !eta_out || max_iter < 0 || !(lambda >= 0.f) || !(tol >= 0.f) || !std::isfinite(L))
         return ISAM_EINVAL;
+    if (resume && (!resume->data || resume->k < 0 || !(resume->t >= 1.0) || !std::isfinite(resume->t)))
+        return ISAM_EINVAL;
+    if (save && !save->data) return ISAM_EINVAL;
     const size_t n = (size_t)p->ncol * p->nk;
     if (overlaps(y, n * 4, eta_out, n * 8)) return ISAM_EALIAS;
     if (w && overlaps(w, n * 4, eta_out, n * 8)) return ISAM_EALIAS;
+    if (save && (overlaps(save->data, 2 * n * 8, eta_out, n * 8) || overlaps(save->data, 2 * n * 8, y, n * 4) ||
+                 (w && overlaps(save->data, 2 * n * 8, w, n * 4))))
+        return ISAM_EALIAS;
     hipStream_t s = (hipStream_t)stream;
     if (L <= 0) {
         const int rc = isam_lipschitz(p, 50, 0, nullptr, &L, stream);
         if (rc) return rc;
     }
+    if (history && max_iter > p->hist_cap) {
+        double* h = nullptr;
+        if (hipStreamSynchronize(s) != hipSuccess) return ISAM_EHIP;
+        if (hipMalloc((void**)&h, (size_t)max_iter * 3 * sizeof(double)) != hipSuccess) return ISAM_ENOMEM;
+        if (p->hist) (void)hipFree(p->hist);
+        p->hist = h;
+        p->hist_cap = max_iter;
+    }
     {
         const int rc = isam::fista_prepare(p, y, w, s);
         if (rc) return rc;
+    }
+    // resume: the momentum point (lateral spectrum) and the last iterate, as saved
+    const int kbase = resume ? resume->k : 0;
+    if (resume) {
+        HIP_OK(hipMemcpyAsync(p->fista_hat, resume->data, n * sizeof(float2), hipMemcpyDeviceToDevice, s));
+        HIP_OK(hipMemcpyAsync(p->zblk, (const float2*)resume->data + n, n * sizeof(float2),
+                              hipMemcpyDeviceToDevice, s));
     }
     float2* z = p->zblk;
     float* wb = w ? p->wbuf : nullptr;
@@ -470,23 +514,26 @@ extern "C" int isam_fista(isam_plan_t p, const float* y, float lambda, const flo
     FistaStep fs;
     fs.step = (float)(1.0 / L);
     fs.lam = lambda;
-    fs.norms = tol > 0.f;
+    fs.norms = tol > 0.f || history != nullptr;
     // Without the Eq. 15 norms (which need g_hat itself) the adjoint of a B-scan writes the
     // gradient step eta_hat - g_hat / L, so the update pass reads one array instead of two.
     // (A volume's adjoint output still passes through its y transform first.)
     fs.pre = !fs.norms && p->ny == 1;
-    // With a tolerance, Eq. 15 is evaluated on the device after every update pass; once it
-    // holds, every later solver kernel returns at once, so the state stays that of the
-    // stopping iteration.  The host reads the stop state every kPoll iterations.
+    // With the norms, Eq. 15 (and the history row) is evaluated on the device after every
+    // update pass; once a stop holds, every later solver kernel returns at once, so the state
+    // stays that of the stopping iteration.  With a tolerance the host reads the stop state
+    // every kPoll iterations.
     constexpr int kPoll = 16;
     const int* stop = fs.norms ? &p->stop->iter : nullptr;
     fs.stop = stop;
     hipLaunchKernelGGL(k_stop_reset, dim3(1), dim3(64), 0, s, p->stop);
     HIP_OK(hipGetLastError());
     const bool vol = p->ny > 1;
-    double t = 1.0, rel_res = -1.0;
-    int iters_run = max_iter, status = ISAM_OK;
-    for (int k = 1; k <= max_iter; ++k) {
+    const double t_start = resume ? resume->t : 1.0;
+    double t = t_start;
+    bool polled_stop = false;
+    for (int it = 1; it <= max_iter; ++it) {
+        const int k = kbase + it;
         // the momentum point lives in the x spectrum; a volume's NUFFT needs the y transform too
         const float2* eh = p->fista_hat;
         if (vol) {
@@ -504,37 +551,62 @@ extern "C" int isam_fista(isam_plan_t p, const float* y, float lambda, const flo
         fs.beta = (float)((t - 1.0) / t_next);
         TIMED(6, lat_fista(p, p->fista_hat, gx, z, wb, fs, part_f, s));
         if (fs.norms) {
-            hipLaunchKernelGGL(k_stop_check, dim3(1), dim3(256), 0, s, part_f, fb, p->stop, k, tol);
+            hipLaunchKernelGGL(k_stop_check, dim3(1), dim3(256), 0, s, part_f, fb, part_r, rb, p->stop, k, tol,
+                               history ? p->hist : nullptr, it - 1);
             HIP_OK(hipGetLastError());
-            if (k % kPoll == 0 || k == max_iter) {
+            if (tol > 0.f && (it % kPoll == 0 || it == max_iter)) {
                 HIP_OK(hipMemcpyAsync(p->host_stop, p->stop, sizeof(isam::StopState), hipMemcpyDeviceToHost, s));
                 HIP_OK(hipStreamSynchronize(s));
-                if (p->host_stop->iter) break;
+                polled_stop = it == max_iter;
+                if (p->host_stop->iter) {
+                    polled_stop = true;
+                    break;
+                }
             }
         }
         t = t_next;
     }
-    if (fs.norms && max_iter > 0) {          // the last loop pass read the stop state
-        rel_res = p->host_stop->rel_res;
-        if (p->host_stop->iter) iters_run = p->host_stop->iter;
-        status = p->host_stop->status;
-    }
-    double resid2 = 0.0, l1 = 0.0;
+    // One synchronisation at the end: the stop state (if not just read), the final norms
+    // (||A eta^k - y||^2 from the last forward pass into sums[0], the update pass's four into
+    // sums[1..4]), the output, the saved state and the history are all enqueued first.
+    if (fs.norms && max_iter > 0 && !polled_stop)
+        HIP_OK(hipMemcpyAsync(p->host_stop, p->stop, sizeof(isam::StopState), hipMemcpyDeviceToHost, s));
     if (max_iter > 0) {
-        int rc = sum_to_host(p, part_r, rb, 1, 0, s);
-        if (rc) return rc;
-        resid2 = p->host_sums[0];
-        rc = sum_to_host(p, part_f, fb, 4, 0, s);
-        if (rc) return rc;
-        l1 = p->host_sums[3];
-        if (!std::isfinite(resid2) || !std::isfinite(l1)) status = ISAM_ENONFINITE;
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, part_r, rb, 1, p->red.sums, 0);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, part_f, fb, 4, p->red.sums + 1, 0);
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipMemcpyAsync(p->host_sums, p->red.sums, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    if (save) {
+        HIP_OK(hipMemcpyAsync(save->data, p->fista_hat, n * sizeof(float2), hipMemcpyDeviceToDevice, s));
+        HIP_OK(hipMemcpyAsync((float2*)save->data + n, p->zblk, n * sizeof(float2), hipMemcpyDeviceToDevice, s));
     }
     {
-        const int rc = isam::fista_finish(p, L, add_residual && status == ISAM_OK, (float2*)eta_out, s);
+        const int rc = isam::fista_finish(p, L, add_residual, (float2*)eta_out, s);
         if (rc) return rc;
     }
     HIP_OK(hipStreamSynchronize(s));
     isam_timing_collect(p);
+    int iters_run = max_iter, status = ISAM_OK;
+    double rel_res = -1.0, resid2 = 0.0, l1 = 0.0;
+    if (fs.norms && max_iter > 0) {
+        if (tol > 0.f) rel_res = p->host_stop->rel_res;
+        if (p->host_stop->iter) iters_run = p->host_stop->iter - kbase;
+        status = p->host_stop->status;
+    }
+    if (max_iter > 0) {
+        resid2 = p->host_sums[0];
+        l1 = p->host_sums[4];
+        if (!std::isfinite(resid2) || !std::isfinite(l1)) status = ISAM_ENONFINITE;
+    }
+    if (history && iters_run > 0) HIP_OK(hipMemcpy(history, p->hist, (size_t)iters_run * 3 * sizeof(double),
+                                                   hipMemcpyDeviceToHost));
+    if (save) {
+        double ts = t_start;
+        for (int i = 0; i < iters_run; ++i) ts = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * ts * ts));
+        save->k = kbase + iters_run;
+        save->t = ts;
+    }
     if (info) {
         info->iters_run = iters_run;
         info->status = status;
@@ -544,6 +616,24 @@ extern "C" int isam_fista(isam_plan_t p, const float* y, float lambda, const flo
         info->L = L;
     }
     return status;
+}
+
+extern "C" int isam_fista(isam_plan_t p, const float* y, float lambda, const float* w, int max_iter,
+                          float tol, double L, int add_residual, void* eta_out, isam_fista_info* info,
+                          void* stream) {
+    return isam_fista_ex(p, y, lambda, w, max_iter, tol, L, add_residual, nullptr, nullptr, nullptr, eta_out,
+                         info, stream);
+}
+
+extern "C" int isam_direct(isam_plan_t p, const float* y, void* eta_out, void* stream) {
+    if (!p || !y || !eta_out) return ISAM_EINVAL;
+    const size_t n = (size_t)p->ncol * p->nk;
+    if (overlaps(y, n * 4, eta_out, n * 8)) return ISAM_EALIAS;
+    hipStream_t s = (hipStream_t)stream;
+    const int t_ = tbegin(p, 8, s);
+    const hipError_t e = direct_image(p, y, (float2*)eta_out, s);
+    tend(p, t_, s);
+    return e == hipSuccess ? ISAM_OK : ISAM_EHIP;
 }
 
 extern "C" int isam_timing(isam_plan_t p, int enable, double* ms_out, int64_t* count_out) {

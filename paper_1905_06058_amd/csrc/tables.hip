@@ -41,11 +41,13 @@ bool is_pow2(long n) { return n > 0 && (n & (n - 1)) == 0; }
 
 struct TableArgs {
     int nx, ny, nk, K;
-    double dx, dy, waist, kc, dk, a2, a3, zf, beta;
+    double dx, dy, waist, kc, dk, dz, a2, a3, zf, beta;
     double* q2;
     float* Bl;
     float2* En;
     float* sm;
+    float2* Dn;
+    float2* Pm;
 };
 
 // Kaiser-Bessel scaling s_m = Psi(0) / Psi(m / K), Psi(u) = sinh(a) / a, a = sqrt(beta^2 - (pi J u)^2).
@@ -71,13 +73,14 @@ __global__ void k_tables(TableArgs a) {
     if (i < a.nk) {
         const double d = (i - a.nk / 2) * a.dk;                   // k_n - k0
         const double k = a.kc + d;
-        double psi = a.a2 * d * d + a.a3 * d * d * d + 2.0 * k * a.zf;
+        double psi = a.a2 * d * d + a.a3 * d * d * d + 2.0 * k * a.zf;   // Eq. 7 (a1 = 0) and focus
         psi -= 2.0 * kPi * rint(psi / (2.0 * kPi));
         double sn, cs;
         sincos(psi, &sn, &cs);
         const double norm = 1.0 / sqrt((double)a.nk);
         a.En[i] = make_float2((float)(cs * norm), (float)(sn * norm));
         a.sm[i] = (float)kb_scale(i - a.nk / 2, a.K, a.beta);
+        direct_table_entry(i, a.nk, a.kc, a.dk, a.dz, a.a2, a.a3, a.Dn[i], a.Pm[i]);     // Eq. 9
     }
 }
 
@@ -327,6 +330,12 @@ void derive(isam_plan_s* p, const isam_geometry* g) {
     p->mi = (int)std::lrint(p->mf);
     p->mr = p->mf - p->mi;
     if (std::fabs(p->mr) < 1e-9) p->mr = 0.0;
+    // Stolt position of the centre sample at q = 0 (kz = 2 kc); the q = 0 column advances by
+    // exactly osf cells per sample from it.  A position within 1e-9 of a grid point is put on
+    // it (an integer lambda_c / dlambda puts every q = 0 sample on the grid).
+    p->t0 = 2.0 * p->kc * p->cT;
+    if (std::fabs(p->t0 - std::rint(p->t0)) < 1e-9) p->t0 = std::rint(p->t0);
+    p->f0 = (int)std::floor(p->t0);
 }
 
 #define HIP_TRY(x)                                  \
@@ -339,7 +348,7 @@ int build_twiddles(isam_plan_s* p, hipStream_t s) {
     // volume the y transform
     struct Item { int N, L; float2* dst; };
     std::vector<Item> items = {{p->K, 4, p->twK}, {p->K, 3, p->twK8}, {p->nx, 2, p->twX[2]}, {p->nx, 3, p->twX[3]},
-                               {p->nx, 4, p->twX[4]}};
+                               {p->nx, 4, p->twX[4]}, {p->nk, 4, p->twN}};
     if (p->ny > 1)       // the y transform of a volume
         for (int L = 2; L <= 4; ++L) items.push_back({p->ny, L, p->twY[L]});
     int ntot = 0;
@@ -383,6 +392,7 @@ int build_calibrated_tables(isam_plan_s* p, hipStream_t s) {
     a.waist = p->g.waist;
     a.kc = p->kc;
     a.dk = p->dk;
+    a.dz = p->dz;
     a.a2 = p->g.a2;
     a.a3 = p->g.a3;
     a.zf = p->g.z_focus;
@@ -391,6 +401,8 @@ int build_calibrated_tables(isam_plan_s* p, hipStream_t s) {
     a.Bl = p->Bl;
     a.En = p->En;
     a.sm = p->sm;
+    a.Dn = p->Dn;
+    a.Pm = p->Pm;
     const int n = std::max(p->ncol, p->nk);
     hipLaunchKernelGGL(k_tables, dim3((n + 255) / 256), dim3(256), 0, s, a);
     HIP_TRY(hipGetLastError());
@@ -426,7 +438,7 @@ int dalloc(T** ptr, size_t n) {
 
 void release(isam_plan_s* p) {
     void* ptrs[] = {p->q2, p->Bl, p->En, p->sm, p->wtab, p->twK, p->twK8, p->twX[2], p->twX[3], p->twX[4],
-                    p->twY[2], p->twY[3], p->twY[4], p->pairs, p->wscratch,
+                    p->twY[2], p->twY[3], p->twY[4], p->pairs, p->wscratch, p->twN, p->Dn, p->Pm, p->hist,
                     p->etahat, p->zh, p->rh, p->ghat, p->fista_hat, p->yhat, p->vec, p->sbuf, p->wbuf, p->zblk,
                     p->xs, p->xsh, p->red.partials, p->red.sums};
     for (void* q : ptrs)
@@ -439,6 +451,20 @@ void release(isam_plan_s* p) {
     delete[] p->tev;
     delete[] p->ttag;
     delete p;
+}
+
+// The adjoint's single-writer slot bounds, checked on the device with the kernels' own Stolt
+// arithmetic (nufft_check): EUNSUPPORTED if any (column, chunk) breaks them.  Synchronises.
+int check_stolt(isam_plan_s* p, hipStream_t s) {
+    int nslots = 0;
+    HIP_TRY(isam::nufft_check(p, p->red.partials, &nslots, s));
+    std::vector<float> flags((size_t)p->ncol * kRedSlots);
+    HIP_TRY(hipMemcpyAsync(flags.data(), p->red.partials, flags.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int c = 0; c < p->ncol; ++c)
+        for (int ch = 0; ch < nslots; ++ch)
+            if (flags[(size_t)c * kRedSlots + ch] != 0.f) return ISAM_EUNSUPPORTED;
+    return ISAM_OK;
 }
 
 }  // namespace
@@ -454,6 +480,9 @@ isam::NufftArgs isam_plan_s::nufft_args() const {
     a.kc = kc;
     a.dk = dk;
     a.cT = cT;
+    a.f0 = f0;
+    a.tau0 = (float)(t0 - f0);
+    a.t0 = t0;
     a.q2 = q2;
     a.Bl = Bl;
     a.En = En;
@@ -473,10 +502,6 @@ extern "C" int isam_plan(const isam_geometry* g, void* stream, isam_plan_t* out)
     *out = nullptr;
     int rc = validate(g);
     if (rc != ISAM_OK) return rc;
-    isam_plan_s probe;
-    derive(&probe, g);
-    if (!isam::nufft_span_ok(&probe)) return ISAM_EUNSUPPORTED;
-
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return ISAM_ENODEV;
     int dev = 0;
@@ -512,6 +537,9 @@ extern "C" int isam_plan(const isam_geometry* g, void* stream, isam_plan_t* out)
     rc = rc ? rc : dalloc(&p->wtab, kWtabEntries);
     rc = rc ? rc : dalloc(&p->twK, fft_stage_len(p->K, 4));
     rc = rc ? rc : dalloc(&p->twK8, fft_stage_len(p->K, 3));
+    rc = rc ? rc : dalloc(&p->twN, fft_stage_len(p->nk, 4));
+    rc = rc ? rc : dalloc(&p->Dn, p->nk);
+    rc = rc ? rc : dalloc(&p->Pm, p->nk);
     for (int L = 2; L <= 4; ++L) rc = rc ? rc : dalloc(&p->twX[L], fft_stage_len(p->nx, L));
     rc = rc ? rc : dalloc(&p->wscratch, 2 * nsums);
     rc = rc ? rc : dalloc(&p->etahat, full);
@@ -534,7 +562,7 @@ extern "C" int isam_plan(const isam_geometry* g, void* stream, isam_plan_t* out)
     hipStream_t s = (hipStream_t)stream;
     if (rc == ISAM_OK) rc = build_twiddles(p, s);
     if (rc == ISAM_OK) rc = build_calibrated_tables(p, s);
-    if (rc == ISAM_OK && hipStreamSynchronize(s) != hipSuccess) rc = ISAM_EHIP;
+    if (rc == ISAM_OK) rc = check_stolt(p, s);
     if (rc != ISAM_OK) {
         release(p);
         return rc;

@@ -29,12 +29,12 @@ EXPORTS = (
     "isam_plan_dims", "isam_timing", "isam_calibration_grad",
     "isam_batch_plan", "isam_batch_offsets", "isam_batch_scan_plan", "isam_batch_set_calibration",
     "isam_batch_forward", "isam_batch_adjoint", "isam_batch_fista", "isam_batch_tune", "isam_batch_tiles",
-    "isam_batch_set_tiles", "isam_batch_destroy",
+    "isam_batch_set_tiles", "isam_batch_destroy", "isam_fista_ex", "isam_fista_state_bytes", "isam_direct",
 )
 ISAM_BATCH_NO_GRAPH = 1
 
 PASS_NAMES = ("lateral_fft_fwd", "nufft_fwd", "lateral_c2r", "lateral_r2c", "nufft_adj",
-              "lateral_fft_inv", "fista_update", "lateral_y")
+              "lateral_fft_inv", "fista_update", "lateral_y", "direct")
 
 
 class IsamError(RuntimeError):
@@ -70,6 +70,10 @@ class Geometry(ctypes.Structure):
         return cls(**vals)
 
 
+class FistaStateRec(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("t", ctypes.c_double), ("data", ctypes.c_void_p)]
+
+
 class FistaInfo(ctypes.Structure):
     _fields_ = [
         ("iters_run", ctypes.c_int32), ("status", ctypes.c_int32), ("rel_res", ctypes.c_double),
@@ -98,6 +102,11 @@ def load_library() -> ctypes.CDLL:
         lib.isam_lambda_max.argtypes = [vp, vp, vp, ctypes.POINTER(dbl), vp]
         lib.isam_fista.argtypes = [vp, vp, f32, vp, ctypes.c_int, f32, dbl, ctypes.c_int, vp,
                                    ctypes.POINTER(FistaInfo), vp]
+        lib.isam_fista_ex.argtypes = [vp, vp, f32, vp, ctypes.c_int, f32, dbl, ctypes.c_int,
+                                      ctypes.POINTER(FistaStateRec), ctypes.POINTER(FistaStateRec),
+                                      ctypes.POINTER(dbl), vp, ctypes.POINTER(FistaInfo), vp]
+        lib.isam_fista_state_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+        lib.isam_direct.argtypes = [vp, vp, vp, vp]
         lib.isam_destroy.argtypes = [vp]
         lib.isam_destroy.restype = None
         lib.isam_strerror.argtypes = [ctypes.c_int]
@@ -162,6 +171,23 @@ class FistaResult:
     resid2: float
     l1: float
     L: float
+    history: object = None        # (iters, 3) float64 numpy array: r_r, ||A eta - y||^2, sum w|z|
+
+
+class FistaState:
+    """A FISTA checkpoint: iterations done, the momentum value t, and a device buffer holding
+    the momentum point and last iterate (opaque layout of the plan that saved it)."""
+
+    def __init__(self, plan: "Plan", device=None):
+        nbytes = ctypes.c_int64()
+        _check(plan._lib.isam_fista_state_bytes(plan._h, ctypes.byref(nbytes)), "isam_fista_state_bytes")
+        self.buffer = torch.empty(int(nbytes.value), dtype=torch.uint8,
+                                  device=device if device is not None else torch.device("cuda"))
+        self.k = 0
+        self.t = 1.0
+
+    def _rec(self) -> FistaStateRec:
+        return FistaStateRec(self.k, self.t, self.buffer.data_ptr())
 
 
 class Plan:
@@ -265,18 +291,47 @@ class Plan:
 
     def fista(self, y: torch.Tensor, lam: float, iters: int, w: torch.Tensor | None = None,
               tol: float = 0.0, L: float = 0.0, add_residual: bool = False,
-              out: torch.Tensor | None = None, stream=None) -> FistaResult:
+              out: torch.Tensor | None = None, resume: "FistaState | None" = None,
+              save: "FistaState | None" = None, history: bool = False, stream=None) -> FistaResult:
+        """Alg. 1.  resume / save: FistaState checkpoints (save is updated in place; it may be
+        the resume state); history: also return the per-iteration records."""
         _dev_tensor(y, torch.float32, self.shape, "y")
         wp = None if w is None else _dev_tensor(w, torch.float32, self.shape, "w").data_ptr()
         if out is None:
             out = torch.empty(self.shape, dtype=torch.complex64, device=y.device)
         _dev_tensor(out, torch.complex64, self.shape, "out")
         info = FistaInfo()
-        code = self._lib.isam_fista(self._h, y.data_ptr(), float(lam), wp, int(iters), float(tol),
-                                    float(L), int(bool(add_residual)), out.data_ptr(),
-                                    ctypes.byref(info), _stream(stream))
-        _check(code, "isam_fista")
-        return FistaResult(out, info.iters_run, info.status, info.rel_res, info.resid2, info.l1, info.L)
+        if resume is None and save is None and not history:
+            code = self._lib.isam_fista(self._h, y.data_ptr(), float(lam), wp, int(iters), float(tol),
+                                        float(L), int(bool(add_residual)), out.data_ptr(),
+                                        ctypes.byref(info), _stream(stream))
+            _check(code, "isam_fista")
+            return FistaResult(out, info.iters_run, info.status, info.rel_res, info.resid2, info.l1, info.L)
+        rin = resume._rec() if resume is not None else None
+        rout = save._rec() if save is not None else None
+        hist = (ctypes.c_double * (3 * max(int(iters), 1)))() if history else None
+        code = self._lib.isam_fista_ex(self._h, y.data_ptr(), float(lam), wp, int(iters), float(tol),
+                                       float(L), int(bool(add_residual)),
+                                       ctypes.byref(rin) if rin is not None else None,
+                                       ctypes.byref(rout) if rout is not None else None,
+                                       hist, out.data_ptr(), ctypes.byref(info), _stream(stream))
+        _check(code, "isam_fista_ex")
+        if save is not None:
+            save.k, save.t = int(rout.k), float(rout.t)
+        h = None
+        if history:
+            import numpy as np
+            h = np.ctypeslib.as_array(hist)[:3 * info.iters_run].reshape(info.iters_run, 3).copy()
+        return FistaResult(out, info.iters_run, info.status, info.rel_res, info.resid2, info.l1, info.L, h)
+
+    def direct(self, y: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """The direct IFFT image of Eq. 9 (dispersion-compensated per-A-scan transform)."""
+        _dev_tensor(y, torch.float32, self.shape, "y")
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.complex64, device=y.device)
+        _dev_tensor(out, torch.complex64, self.shape, "out")
+        _check(self._lib.isam_direct(self._h, y.data_ptr(), out.data_ptr(), _stream(stream)), "isam_direct")
+        return out
 
 
 class _BorrowedPlan(Plan):

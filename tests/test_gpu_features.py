@@ -1,0 +1,160 @@
+"""GPU: solver features and robustness, against the FP64 oracle where it applies.
+
+* FISTA checkpoint / resume (Alg. 1 state k, t, eta^{k+1}, z^k): a + b iterations equal a + b
+  in one call bit for bit, and match the oracle's resumed run;
+* per-iteration records (r_r of Eq. 15, ||A eta^k - y||^2, sum w|z^k|) against the oracle's;
+* NaN in the measured spectra -> ISAM_ENONFINITE from FISTA and lambda_max;
+* optics whose lambda_c / dlambda is an integer (800 / 100 nm, the class of the paper's
+  800 nm system, and 1300 / 130 nm): every q = 0 Stolt point lies on the oversampled grid;
+  the plan's slot-bound check passes and the operator matches the oracle;
+* the direct image of Eq. 9 on small B-scans and on a volume (A-scans independent).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import phantoms as ph
+from _util import rel, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+TOL_OP = 1e-5
+TOL_FISTA = 1e-4
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1905_06058_amd as pkg
+    pkg.load_library()
+    return pkg
+
+
+def tiny_problem():
+    w = ph.workload("tiny")
+    g = O.Geometry.of(w.optics)
+    op = O.Operator(g, "N")
+    y = ph.add_noise(op.A(ph.phantom(w)), w.snr_db, w.seed)
+    return w, g, op, y
+
+
+def test_fista_resume_is_bitwise_and_matches_oracle(P):
+    import torch
+    w, g, op, y = tiny_problem()
+    yd = to_dev(y)
+    with P.Plan(P.Geometry.of(w.optics)) as plan:
+        L = plan.lipschitz(iters=50, seed=0)
+        lam = 0.05 * plan.lambda_max(yd)
+        full = plan.fista(yd, lam, 100, L=L)
+        z_full = full.eta.clone()
+        st = P.FistaState(plan)
+        a = plan.fista(yd, lam, 50, L=L, save=st)
+        assert st.k == 50 and a.iters == 50
+        b = plan.fista(yd, lam, 50, L=L, resume=st, save=st)
+        assert st.k == 100
+        assert torch.equal(b.eta, z_full)
+        assert b.resid2 == full.resid2 and b.l1 == full.l1
+        # three legs with a zero-iteration call in between return the saved iterate
+        st2 = P.FistaState(plan)
+        plan.fista(yd, lam, 30, L=L, save=st2)
+        mid = plan.fista(yd, lam, 0, L=L, resume=st2)
+        c = plan.fista(yd, lam, 70, L=L, resume=st2)
+        assert torch.equal(c.eta, z_full)
+    ra = O.fista(op, y, lam, L, 50)
+    rb = O.fista(op, y, lam, L, 50, state=ra.state)
+    assert rel(to_host(b.eta), rb.z) < TOL_FISTA
+    assert rel(to_host(mid.eta), O.fista(op, y, lam, L, 30).z) < TOL_FISTA
+    t = 1.0
+    for _ in range(100):
+        t = (1 + math.sqrt(1 + 4 * t * t)) / 2
+    assert abs(st.t - t) < 1e-12 * t
+
+
+def test_fista_history_matches_oracle(P):
+    w, g, op, y = tiny_problem()
+    wts = ph.depth_weights(g.nx, g.nk)
+    with P.Plan(P.Geometry.of(w.optics)) as plan:
+        L = plan.lipschitz(iters=50, seed=0)
+        lam = 0.05 * plan.lambda_max(to_dev(y), to_dev(wts))
+        res = plan.fista(to_dev(y), lam, 60, L=L, w=to_dev(wts), history=True)
+        plain = plan.fista(to_dev(y), lam, 60, L=L, w=to_dev(wts))
+    ref = O.fista(op, y, lam, L, 60, w=wts)
+    h = res.history
+    assert h.shape == (60, 3)
+    assert rel(to_host(res.eta), ref.z) < TOL_FISTA
+    assert rel(to_host(res.eta), to_host(plain.eta)) < 2e-6
+    assert np.all(np.abs(h[:, 1] - ref.resid2) <= 1e-4 * np.asarray(ref.resid2))
+    assert np.all(np.abs(h[:, 2] - ref.l1) <= 1e-4 * np.maximum(np.asarray(ref.l1), 1e-30))
+    rr = np.asarray(ref.rel_res)
+    assert np.all(np.abs(h[:, 0] - rr) <= 1e-3 * rr + 1e-6)
+
+
+def test_nan_in_data_is_reported(P):
+    w, g, op, y = tiny_problem()
+    bad = y.copy()
+    bad[5, 17] = np.nan
+    with P.Plan(P.Geometry.of(w.optics)) as plan:
+        with pytest.raises(P.IsamError) as ei:
+            plan.fista(to_dev(bad), 0.1, 10, L=1.01)
+        assert ei.value.code == -7
+        with pytest.raises(P.IsamError) as ei:
+            plan.fista(to_dev(bad), 0.1, 10, L=1.01, tol=1e-3)
+        assert ei.value.code == -7
+        with pytest.raises(P.IsamError) as ei:
+            plan.lambda_max(to_dev(bad))
+        assert ei.value.code == -7
+        # the plan still works afterwards
+        res = plan.fista(to_dev(y), 0.1, 10, L=1.01)
+        assert res.status == 0
+
+
+@pytest.mark.parametrize("lambda_c,dlambda", [(800e-9, 100e-9), (1300e-9, 130e-9)])
+@pytest.mark.parametrize("nx,nk", [(64, 512), (32, 2048)])
+def test_integer_ratio_optics(P, lambda_c, dlambda, nx, nk):
+    """lambda_c / dlambda integer: every q = 0 Stolt position is a grid point (t advances by
+    exactly two cells per sample), the case where a rounded square root could put two
+    consecutive samples one cell apart."""
+    import torch
+    o = ph.custom_optics(nx, nk, lambda_c=lambda_c, dlambda=dlambda, focus_rows=nk // 4)
+    g = O.Geometry.of(o)
+    rng = np.random.default_rng(nx + nk)
+    eta = ph.complex_gaussian(rng, (nx, nk))
+    r = rng.standard_normal((nx, nk))
+    with P.Plan(P.Geometry.of(o)) as plan:
+        s = to_host(plan.forward(to_dev(eta)))
+        a1 = plan.adjoint(to_dev(r)).clone()
+        a2 = plan.adjoint(to_dev(r)).clone()
+        assert torch.equal(a1, a2)
+        x = to_dev(eta)
+        Ax = plan.forward(x).double()
+        lhs = float((Ax * to_dev(r).double()).sum())
+        rhs = float(torch.real(torch.vdot(x.to(torch.complex128).ravel(), a1.to(torch.complex128).ravel())))
+        assert abs(lhs - rhs) / (float(Ax.norm()) * float(np.linalg.norm(r))) < 1e-6
+    assert rel(s, O.forward_nufft(g, eta)) < TOL_OP
+    assert rel(to_host(a1), O.adjoint_nufft(g, r)) < TOL_OP
+
+
+@pytest.mark.parametrize("nx,nk", [(1, 16), (8, 64), (64, 256), (16, 4096)])
+def test_direct_image_matches_oracle(P, nx, nk):
+    o = ph.custom_optics(nx, nk, edge_phase2=30 * math.pi, edge_phase3=6 * math.pi)
+    g = O.Geometry.of(o)
+    rng = np.random.default_rng(nk + nx)
+    y = rng.standard_normal((nx, nk))
+    with P.Plan(P.Geometry.of(o)) as plan:
+        d = to_host(plan.direct(to_dev(y)))
+    assert rel(d, O.direct_image(g, y)) < TOL_OP
+
+
+def test_direct_image_of_a_volume_is_per_ascan(P):
+    ny, nx, nk = 4, 8, 256
+    o = ph.custom_optics(nx, nk)
+    rng = np.random.default_rng(46)
+    y = rng.standard_normal((ny, nx, nk))
+    with P.Plan(P.Geometry.of(o, ny=ny, dy=o.dx)) as plan:
+        d = to_host(plan.direct(to_dev(y)))
+    ref = O.direct_image(O.Geometry.of(o, nx=ny * nx), y.reshape(ny * nx, nk)).reshape(ny, nx, nk)
+    assert rel(d, ref) < TOL_OP
