@@ -52,6 +52,11 @@ def parse():
     return ap.parse_args()
 
 
+def progress(msg: str) -> None:
+    """One line per finished leg on stderr (the JSON result line goes to stdout)."""
+    print(f"bench.py: {msg}", file=sys.stderr, flush=True)
+
+
 def sources_digest() -> str:
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
@@ -124,14 +129,17 @@ def cpu_baseline(w, reps: int) -> dict:
     tb = time.perf_counter()
     op = O.Operator(g, "N", workers=O.default_workers())
     build_s = time.perf_counter() - tb
+    progress(f"oracle interpolation matrices built in {build_s:.1f} s")
     y = ph.add_noise(op.A(ph.phantom(w)), w.snr_db, w.seed)
     lam = w.lam_frac * O.lambda_max(op, y)
     L = 1.01
     with threadpool_limits(limits=1):
         prev = O.set_fft_workers(1)
         t1 = _median_iteration(O, op, y, lam, L, reps)
+    progress(f"oracle single-core iteration {t1:.2f} s")
     O.set_fft_workers(ncores)
     tn = _median_iteration(O, op, y, lam, L, reps)
+    progress(f"oracle {ncores}-core iteration {tn:.2f} s")
     # volume: one pair on a 16 x 16 x 2048 slab (256 of the 65536 columns), all cores
     vo = ph.custom_optics(16, w.optics.nk, edge_phase2=40 * math.pi, edge_phase3=8 * math.pi,
                           focus_rows=w.optics.nk // 4)
@@ -372,6 +380,9 @@ def main() -> int:
     torch.cuda.synchronize()
     direct_s = (time.perf_counter() - td) / max(args.pairs, 1)
 
+    progress(f"operator legs done: {1.0 / pair_s:.0f} pairs/s, {1.0 / normal_s:.0f} normal/s, "
+             f"{1.0 / direct_s:.0f} direct images/s")
+
     # ---- FISTA: warm-up, then exactly `steps` iterations in one timed region
     if args.warmup > 0:
         plan.fista(y, lam, args.warmup, L=L, out=out)
@@ -399,6 +410,9 @@ def main() -> int:
     rtol = plan.fista(y, lam, 5000, L=L, tol=1e-3, out=out)
     torch.cuda.synchronize()
     wall_tol = time.perf_counter() - t0
+
+    progress(f"FISTA {args.steps / wall:.0f} iter/s; with Eq. 15 norms {args.steps / wall15:.0f} iter/s; "
+             f"tol 1e-3 stop after {rtol.iters} iterations")
 
     # ---- per-pass kernel durations (HIP events on the launch stream) over a second FISTA run
     plan.timing(True)
@@ -449,15 +463,21 @@ def main() -> int:
                              "frac_unpacked": round(achieved_tfs / ALU_PEAK_UNPACKED_TFS, 4)}}
     iter_bytes = sum(nbytes[k] for k in ("nufft_fwd", "nufft_adj", "fista_update"))
 
+    progress("per-pass timings done")
     batched = None if args.no_batch else batch_leg(P, torch, args.batch_iters)
+    if batched:
+        progress(f"batch leg done: FISTA x{batched['fista_speedup']}")
     # many small scans, where one launch per pass per scan is dominated by launch latency
     batched_small = None if args.no_batch else batch_leg(
         P, torch, args.batch_iters, nscans=256, nx_choices=(64, 128, 192, 256), nk_choices=(256, 512))
     volume = None if args.no_volume else volume_leg(P, torch, args.volume_iters)
+    if volume:
+        progress(f"volume leg done: {volume['fista_iter_per_s']} iter/s")
 
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, args.cpu_reps)
+        progress(f"cpu baseline done: {cpu['value']} iter/s on {cpu['cores']} cores")
 
     line = {
         "metric": METRIC,
