@@ -213,6 +213,19 @@ int isam_fista_ex(isam_plan_t p, const float* y, float lambda, const float* w, i
  * One nk-point LDS FFT per A-scan.  Errors: EINVAL (NULL), EALIAS. */
 int isam_direct(isam_plan_t p, const float* y, void* eta_out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): isam_direct without a plan.  The tables
+ * the direct image needs (dispersion compensation, row phases, FFT twiddles) are built by a
+ * kernel into a static device array of the library (100 KB, held by each GPU the library
+ * runs on until the process ends); nothing is allocated.  g: geometry (nx, ny, nk,
+ * lambda_c, dlambda, a2, a3 are read); y: device float32 [ny][nx][nk]; eta_out: device
+ * complex64 [ny][nx][nk]; same result as isam_direct on a plan of g.  nk must be a power of
+ * two from 16 to 4096 (the array's capacity): EUNSUPPORTED otherwise.  Every call on a GPU
+ * shares that GPU's array: calls that overlap on one GPU (other streams, other threads)
+ * race and give wrong images; calls on one stream are ordered and safe.  Asynchronous.
+ * Errors: EINVAL (NULL, bad optics), EUNSUPPORTED, EALIAS, ENODEV, EHIP. */
+int isam_direct_static(const isam_geometry* g, const float* y, void* eta_out, void* stream);
+
 /* Per-pass timing (profiling support).  enable = 1 clears the accumulators and
  * makes every later operator / FISTA call on the plan attach a HIP event pair
  * to each pass's kernel launch on its stream (the runtime stamps the pair with

@@ -4,7 +4,7 @@ The computation lives in the HIP library ``libisam.so`` (C ABI in include/isam.h
 this package is its Python binding.
 """
 from .isam import (EXPORTS, Batch, FistaInfo, FistaResult, FistaState, Geometry, IsamError, LIB_PATH,  # noqa: F401
-                   Plan, load_library)
+                   Plan, direct_static, load_library)
 
 __all__ = ["Plan", "Batch", "Geometry", "IsamError", "FistaResult", "FistaInfo", "FistaState", "load_library",
-           "LIB_PATH", "EXPORTS"]
+           "LIB_PATH", "EXPORTS", "direct_static"]

@@ -30,6 +30,7 @@ EXPORTS = (
     "isam_batch_plan", "isam_batch_offsets", "isam_batch_scan_plan", "isam_batch_set_calibration",
     "isam_batch_forward", "isam_batch_adjoint", "isam_batch_fista", "isam_batch_tune", "isam_batch_tiles",
     "isam_batch_set_tiles", "isam_batch_destroy", "isam_fista_ex", "isam_fista_state_bytes", "isam_direct",
+    "isam_direct_static",
 )
 ISAM_BATCH_NO_GRAPH = 1
 
@@ -107,6 +108,7 @@ def load_library() -> ctypes.CDLL:
                                       ctypes.POINTER(dbl), vp, ctypes.POINTER(FistaInfo), vp]
         lib.isam_fista_state_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
         lib.isam_direct.argtypes = [vp, vp, vp, vp]
+        lib.isam_direct_static.argtypes = [ctypes.POINTER(Geometry), vp, vp, vp]
         lib.isam_destroy.argtypes = [vp]
         lib.isam_destroy.restype = None
         lib.isam_strerror.argtypes = [ctypes.c_int]
@@ -332,6 +334,21 @@ class Plan:
         _dev_tensor(out, torch.complex64, self.shape, "out")
         _check(self._lib.isam_direct(self._h, y.data_ptr(), out.data_ptr(), _stream(stream)), "isam_direct")
         return out
+
+
+def direct_static(geometry, y: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """The direct image of Eq. 9 without a plan (isam_direct_static: allocates nothing on the
+    device; its tables live in the library's static array, so concurrent calls on one GPU race)."""
+    lib = load_library()
+    g = geometry if isinstance(geometry, Geometry) else Geometry.of(geometry)
+    shape = (int(g.nx), int(g.nk)) if int(g.ny) == 1 else (int(g.ny), int(g.nx), int(g.nk))
+    _dev_tensor(y, torch.float32, shape, "y")
+    if out is None:
+        out = torch.empty(shape, dtype=torch.complex64, device=y.device)
+    _dev_tensor(out, torch.complex64, shape, "out")
+    _check(lib.isam_direct_static(ctypes.byref(g), y.data_ptr(), out.data_ptr(), _stream(stream)),
+           "isam_direct_static")
+    return out
 
 
 class _BorrowedPlan(Plan):
