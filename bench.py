@@ -115,10 +115,11 @@ def _median_iteration(O, op, y, lam, L, reps):
     return float(sorted(times)[len(times) // 2])
 
 
-def cpu_baseline(w, reps: int) -> dict:
+def cpu_baseline(w, reps: int, P, torch) -> dict:
     """The FP64 oracle (mode N) timed on this host: FISTA iterations on the full workload with
     one core and with every core this process may use, and one A.A^H pair of the 256 x 256 x
-    2048 volume extrapolated from a 16 x 16 slab of columns."""
+    2048 volume extrapolated from a 16 x 16 slab of columns; with the accuracy of the GPU
+    path against it (accuracy_leg)."""
     import numpy as np
     import oracle as O
     import phantoms as ph
@@ -156,6 +157,8 @@ def cpu_baseline(w, reps: int) -> dict:
     O.set_fft_workers(prev)
     pair_slab = sorted(tv)[1]
     scale = (256 * 256) / (16 * 16)
+    accuracy = accuracy_leg(P, torch, w, op, y)
+    progress(f"accuracy against the oracle: {accuracy}")
     return {
         "value": round(1.0 / tn, 4),
         "unit": "iter/s",
@@ -173,7 +176,64 @@ def cpu_baseline(w, reps: int) -> dict:
             "sample": (f"one A.A^H pair on a 16x16x2048 slab of the 256x256x2048 volume ({pair_slab:.2f} s, "
                        f"median of 3), extrapolated linearly in columns (x{scale:.0f}); the 2-D lateral "
                        "FFT's log factor is not scaled, so this overstates the oracle's rate")},
+        "accuracy": accuracy,
     }
+
+
+def accuracy_leg(P, torch, w, op, y) -> dict:
+    """Accuracy reported beside the timings: the GPU's A and A^H against the oracle (mode N)
+    on the workload, the adjoint dot test, the FISTA image after 200 iterations against the
+    oracle's stored iterate (same spectra, L and lambda), and on the 64 x 256 workload the
+    largest ratio of the oracle's NUFFT error to the min-max bound (mode N against mode E)."""
+    import numpy as np
+    import oracle as O
+    import phantoms as ph
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    out = {}
+    eta = ph.phantom(w)
+    with P.Plan(P.Geometry.of(w.optics)) as plan:
+        s = plan.forward(torch.from_numpy(eta).to(torch.complex64).cuda()).double().cpu().numpy()
+        yd = torch.from_numpy(y).float().cuda()
+        a = plan.adjoint(yd).cpu().numpy().astype(np.complex128)
+        out["A_rel_l2"] = rel(s, op.A(eta))
+        out["AH_rel_l2"] = rel(a, op.AH(y))
+        rng = np.random.default_rng(9)
+        x = torch.from_numpy(ph.complex_gaussian(rng, eta.shape)).to(torch.complex64).cuda()
+        r = torch.from_numpy(rng.standard_normal(eta.shape)).float().cuda()
+        Ax = plan.forward(x).double()
+        AHr = plan.adjoint(r).to(torch.complex128)
+        lhs = float((Ax * r.double()).sum())
+        rhs = float(torch.real(torch.vdot(x.to(torch.complex128).ravel(), AHr.ravel())))
+        out["dot_test"] = abs(lhs - rhs) / (float(Ax.norm()) * float(r.double().norm()))
+        golden = os.path.join(ROOT, "tests", "golden", "bscan_fista.npz")
+        if w.name == "bscan" and os.path.exists(golden):
+            gd = np.load(golden)
+            y32 = torch.from_numpy(y.astype(np.float32)).cuda()
+            res = plan.fista(y32, float(gd["lam"]), 200, L=float(gd["L"]))
+            z = res.eta.cpu().numpy().astype(np.complex128).ravel()
+            ref = np.zeros_like(z)
+            ref[gd["idx_200"]] = gd["val_200"]
+            out["fista_z200_rel_l2"] = float(np.linalg.norm(z - ref) / np.linalg.norm(ref))
+    # mode N against mode E on the 64 x 256 workload: the per-point error over the bound
+    t = ph.workload("tiny")
+    g = O.Geometry.of(t.optics)
+    G = O.grids(g)
+    eh = np.fft.fft(ph.phantom(t), axis=0, norm="ortho")
+    kz, _ = O.axial_wavenumber(g)
+    tt, g0, tau = O.stolt_points(g)
+    Eb = O.minmax_error(g, tau.ravel()).reshape(tau.shape)
+    worst = 0.0
+    for l in range(g.nx):
+        col = np.linalg.norm(eh[l])
+        X = np.exp(1j * kz[l][:, None] * G.z[None, :]) @ eh[l] / math.sqrt(g.nk)
+        Y = O.isam_oracle._oversampled_spectrum(g, eh[l])[0]
+        Xh = O.isam_oracle._interp_matrix(g, l, None, (tt, g0, tau)) @ Y / math.sqrt(g.nk)
+        worst = max(worst, float((np.abs(Xh - X) / (Eb[l] * col)).max()))
+    out["tiny_nufft_bound_utilisation"] = worst
+    return out
 
 
 def batch_leg(P, torch, iters: int, nscans: int = 64, nx_choices=tuple(range(256, 1025, 128)),
@@ -475,9 +535,11 @@ def main() -> int:
         progress(f"volume leg done: {volume['fista_iter_per_s']} iter/s")
 
     cpu = None
+    accuracy = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w, args.cpu_reps)
+        cpu = cpu_baseline(w, args.cpu_reps, P, torch)
         progress(f"cpu baseline done: {cpu['value']} iter/s on {cpu['cores']} cores")
+        accuracy = cpu["accuracy"]
 
     line = {
         "metric": METRIC,
@@ -513,6 +575,7 @@ def main() -> int:
         "batched_small_scans": batched_small,
         "volume": volume,
         "cpu_baseline": cpu,
+        "accuracy": accuracy,
         "gpu": torch.cuda.get_device_name(0),
     }
     print(json.dumps(line))

@@ -226,6 +226,19 @@ int isam_direct(isam_plan_t p, const float* y, void* eta_out, void* stream);
  * Errors: EINVAL (NULL, bad optics), EUNSUPPORTED, EALIAS, ENODEV, EHIP. */
 int isam_direct_static(const isam_geometry* g, const float* y, void* eta_out, void* stream);
 
+/* Plan inspection (testing and diagnostics).  isam_plan_stolt writes, for lateral-frequency
+ * column col (FFT order; col = lx * ny + ly for a volume) and every sample n < nk, the
+ * oversampled grid position the NUFFT kernels use (Eq. 3 on the K = 2 nz grid): fl_out[n] =
+ * floor(t), not reduced mod K, and tau_out[n] = t - floor(t); -1 for evanescent samples.
+ * fl_out: device int32 [nk]; tau_out: device float32 [nk].  isam_plan_weights evaluates the
+ * plan's min-max weight table (the interpolator the paper adopts, Sec. "Efficient and robust
+ * ISAM through non-uniform FFT") as the kernels do, at tau (device float32 [n], in [0, 1)):
+ * w_out (device complex64 [n][6]) receives u_1..u_6(tau), times the integer focal row's phase
+ * e^{-2 pi i mi (tau + 3 - j) / K} that the plan folds into the table (none for z_focus = 0).
+ * Both asynchronous.  Errors: EINVAL. */
+int isam_plan_stolt(isam_plan_t p, int col, int32_t* fl_out, float* tau_out, void* stream);
+int isam_plan_weights(isam_plan_t p, const float* tau, int n, void* w_out, void* stream);
+
 /* Per-pass timing (profiling support).  enable = 1 clears the accumulators and
  * makes every later operator / FISTA call on the plan attach a HIP event pair
  * to each pass's kernel launch on its stream (the runtime stamps the pair with

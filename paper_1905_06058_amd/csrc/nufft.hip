@@ -785,6 +785,45 @@ __global__ __launch_bounds__(256) void k_nufft_check(NufftArgs a, float* __restr
 
 }  // namespace
 
+namespace {
+
+// Plan inspection: the Stolt points of one column exactly as the kernels compute them, and
+// the weight table evaluated as the kernels evaluate it (testing and diagnostics).
+__global__ void k_inspect_stolt(NufftArgs a, int col, int* __restrict__ fl_out, float* __restrict__ tau_out) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= a.nk) return;
+    double t;
+    int fl = 0;
+    float tau = 0.f;
+    if (!stolt_point(a, a.q2[col], n, t, fl, tau)) {
+        fl = -1;
+        tau = -1.f;
+    }
+    fl_out[n] = fl;
+    tau_out[n] = tau;
+}
+
+__global__ void k_inspect_weights(const float2* __restrict__ wtab, const float* __restrict__ tau, int n,
+                                  float2* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float t = fminf(fmaxf(tau[i], 0.f), 0.99999994f);
+#pragma unroll
+    for (int jj = 0; jj < kJ; ++jj) out[i * kJ + jj] = weight(wtab, t, jj);
+}
+
+}  // namespace
+
+hipError_t inspect_stolt(const isam_plan_s* p, int col, int* fl, float* tau, hipStream_t s) {
+    hipLaunchKernelGGL(k_inspect_stolt, dim3((p->nk + 255) / 256), dim3(256), 0, s, p->nufft_args(), col, fl, tau);
+    return hipGetLastError();
+}
+
+hipError_t inspect_weights(const isam_plan_s* p, const float* tau, int n, float2* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_inspect_weights, dim3((n + 255) / 256), dim3(256), 0, s, p->wtab, tau, n, out);
+    return hipGetLastError();
+}
+
 hipError_t nufft_check(const isam_plan_s* p, float* partials, int* nslots, hipStream_t s) {
     ISAM_K_SWITCH(p->K, {
         const int n = p->ncol * NuAdjCfg<K>::NCH;

@@ -220,7 +220,9 @@ hipError_t nufft_adj_batch(int K, const NuScan* recs, const int2* map, int nblk,
 int lat_tile(int nx, int sel, int real);        // lanes per tile built for (nx, sel)
 int lat_radix_cap(int nx, int sel, int real);   // radix cap (log2) of that configuration
 // FISTA set-up and output steps shared by the single and batched solvers (solver.hip).
-int fista_prepare(isam_plan_t p, const float* y, const float* w, hipStream_t s);
+// zero_state: start from eta^1 = z^0 = 0 (false: the caller restores a saved state).  Also
+// resets the plan's device stop state.
+int fista_prepare(isam_plan_t p, const float* y, const float* w, hipStream_t s, bool zero_state = true);
 int fista_finish(isam_plan_t p, double L, int add_residual, float2* out, hipStream_t s);
 // Whether a lateral length has built kernels (powers of two up to 2048 and 3, 5, 7 times
 // powers of two from 192 up to 1792).
@@ -235,6 +237,9 @@ hipError_t nufft_calgrad(const isam_plan_s* p, const float2* etahat, const float
 // Device check, with the kernels' own Stolt arithmetic, of the two bounds the adjoint's
 // single-writer slots rely on; writes one flag per (column, chunk) into partials.
 hipError_t nufft_check(const isam_plan_s* p, float* partials, int* nslots, hipStream_t s);
+// Plan inspection (isam_plan_stolt, isam_plan_weights).
+hipError_t inspect_stolt(const isam_plan_s* p, int col, int* fl, float* tau, hipStream_t s);
+hipError_t inspect_weights(const isam_plan_s* p, const float* tau, int n, float2* out, hipStream_t s);
 // Direct image of Eq. 9 (per A-scan dispersion compensation and inverse transform).
 hipError_t direct_image(const isam_plan_s* p, const float* y, float2* out, hipStream_t s);
 

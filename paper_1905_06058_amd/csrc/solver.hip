@@ -29,8 +29,8 @@ ISAM_DEV float nan_maxf(float a, float b) { return a != a ? a : (b != b ? b : fm
 // FP64 sums (or maxima) of the per-workgroup partials: strided per-thread sums, then a
 // fixed-order tree, so the result does not depend on scheduling.
 
-__global__ __launch_bounds__(256) void k_finalize(const float* __restrict__ partials, int nblocks,
-                                                  int nslots, double* __restrict__ sums, int mode_max) {
+ISAM_DEV void finalize_block(const float* __restrict__ partials, int nblocks, int nslots,
+                             double* __restrict__ sums, int mode_max) {
     __shared__ double sh[256];
     const int tid = threadIdx.x;
     for (int s = 0; s < nslots; ++s) {
@@ -48,6 +48,19 @@ __global__ __launch_bounds__(256) void k_finalize(const float* __restrict__ part
         if (tid == 0) sums[s] = sh[0];
         __syncthreads();
     }
+}
+
+__global__ __launch_bounds__(256) void k_finalize(const float* __restrict__ partials, int nblocks,
+                                                  int nslots, double* __restrict__ sums, int mode_max) {
+    finalize_block(partials, nblocks, nslots, sums, mode_max);
+}
+
+// Two independent sums in one launch (block 0: a, block 1: b), as k_finalize.
+__global__ __launch_bounds__(256) void k_finalize2(const float* __restrict__ pa, int na, int sa, double* __restrict__ da,
+                                                   const float* __restrict__ pb, int nb, int sb,
+                                                   double* __restrict__ db) {
+    if (blockIdx.x == 0) finalize_block(pa, na, sa, da, 0);
+    else finalize_block(pb, nb, sb, db, 0);
 }
 
 // Per-iteration record of the solve on the device (Eq. 15).  Sums slots 0..3 of the update
@@ -89,14 +102,6 @@ __global__ __launch_bounds__(256) void k_stop_check(const float* __restrict__ pa
             st->rel_res = rr;
             if (tol > 0.f && rr < (double)tol) st->iter = k;
         }
-    }
-}
-
-__global__ void k_stop_reset(isam::StopState* st) {
-    if (threadIdx.x == 0) {
-        st->iter = 0;
-        st->status = ISAM_OK;
-        st->rel_res = -1.0;
     }
 }
 
@@ -162,6 +167,22 @@ __global__ void k_from_blk_c(const float2* __restrict__ src, float2* __restrict_
 __global__ void k_zero(float2* __restrict__ x, size_t n) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         x[i] = c2(0.f, 0.f);
+}
+
+// FISTA start (Alg. 1: eta^1 = z^0 = 0): zero both state arrays (unless zero is 0) and reset
+// the device stop state, in one launch.
+__global__ void k_fista_init(float2* __restrict__ a, float2* __restrict__ b, size_t n, int zero,
+                             isam::StopState* st) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->iter = 0;
+        st->status = ISAM_OK;
+        st->rel_res = -1.0;
+    }
+    if (!zero) return;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        a[i] = c2(0.f, 0.f);
+        b[i] = c2(0.f, 0.f);
+    }
 }
 
 // Counter-based complex Gaussian start vector: SplitMix64 (Steele, Lea & Flood 2014)
@@ -432,12 +453,12 @@ namespace isam {
 
 // FISTA set-up (Alg. 1 with eta^1 = z^0 = 0): zero the state, bring the weights into the
 // blocked layout, and form the data's lateral spectrum yhat = F(y) (Hermitian half, blocked).
-int fista_prepare(isam_plan_t p, const float* y, const float* w, hipStream_t s) {
+int fista_prepare(isam_plan_t p, const float* y, const float* w, hipStream_t s, bool zero_state) {
     const size_t n = (size_t)p->ncol * p->nk;
     const int gb = grid_for(n);
     if (nufft_fwd_blocks(p) + lat_blocks(p, 0) > p->red.maxBlocks) return ISAM_EUNSUPPORTED;
-    hipLaunchKernelGGL(k_zero, dim3(gb), dim3(256), 0, s, p->zblk, n);
-    hipLaunchKernelGGL(k_zero, dim3(gb), dim3(256), 0, s, p->fista_hat, n);
+    hipLaunchKernelGGL(k_fista_init, dim3(zero_state ? gb : 1), dim3(256), 0, s, p->zblk, p->fista_hat, n,
+                       zero_state ? 1 : 0, p->stop);
     if (w) hipLaunchKernelGGL(k_to_blk_f, dim3(gb), dim3(256), 0, s, w, p->wbuf, p->nx, p->nk, p->ny);
     HIP_OK(hipGetLastError());
     return lat_from_real(p, y, p->yhat, s);
@@ -496,7 +517,7 @@ extern "C" int isam_fista_ex(isam_plan_t p, const float* y, float lambda, const 
         p->hist_cap = max_iter;
     }
     {
-        const int rc = isam::fista_prepare(p, y, w, s);
+        const int rc = isam::fista_prepare(p, y, w, s, resume == nullptr);
         if (rc) return rc;
     }
     // resume: the momentum point (lateral spectrum) and the last iterate, as saved
@@ -526,8 +547,6 @@ extern "C" int isam_fista_ex(isam_plan_t p, const float* y, float lambda, const 
     constexpr int kPoll = 16;
     const int* stop = fs.norms ? &p->stop->iter : nullptr;
     fs.stop = stop;
-    hipLaunchKernelGGL(k_stop_reset, dim3(1), dim3(64), 0, s, p->stop);
-    HIP_OK(hipGetLastError());
     const bool vol = p->ny > 1;
     const double t_start = resume ? resume->t : 1.0;
     double t = t_start;
@@ -572,8 +591,8 @@ extern "C" int isam_fista_ex(isam_plan_t p, const float* y, float lambda, const 
     if (fs.norms && max_iter > 0 && !polled_stop)
         HIP_OK(hipMemcpyAsync(p->host_stop, p->stop, sizeof(isam::StopState), hipMemcpyDeviceToHost, s));
     if (max_iter > 0) {
-        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, part_r, rb, 1, p->red.sums, 0);
-        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, part_f, fb, 4, p->red.sums + 1, 0);
+        hipLaunchKernelGGL(k_finalize2, dim3(2), dim3(256), 0, s, part_r, rb, 1, p->red.sums, part_f, fb, 4,
+                           p->red.sums + 1);
         HIP_OK(hipGetLastError());
         HIP_OK(hipMemcpyAsync(p->host_sums, p->red.sums, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
     }
@@ -623,6 +642,17 @@ extern "C" int isam_fista(isam_plan_t p, const float* y, float lambda, const flo
                           void* stream) {
     return isam_fista_ex(p, y, lambda, w, max_iter, tol, L, add_residual, nullptr, nullptr, nullptr, eta_out,
                          info, stream);
+}
+
+extern "C" int isam_plan_stolt(isam_plan_t p, int col, int32_t* fl_out, float* tau_out, void* stream) {
+    if (!p || !fl_out || !tau_out || col < 0 || col >= p->ncol) return ISAM_EINVAL;
+    return inspect_stolt(p, col, fl_out, tau_out, (hipStream_t)stream) == hipSuccess ? ISAM_OK : ISAM_EHIP;
+}
+
+extern "C" int isam_plan_weights(isam_plan_t p, const float* tau, int n, void* w_out, void* stream) {
+    if (!p || !tau || !w_out || n < 0) return ISAM_EINVAL;
+    if (n == 0) return ISAM_OK;
+    return inspect_weights(p, tau, n, (float2*)w_out, (hipStream_t)stream) == hipSuccess ? ISAM_OK : ISAM_EHIP;
 }
 
 extern "C" int isam_direct(isam_plan_t p, const float* y, void* eta_out, void* stream) {

@@ -427,8 +427,17 @@ int build_calibrated_tables(isam_plan_s* p, hipStream_t s) {
     return ISAM_OK;
 }
 
+// Failure injection for tests of the clean-up path: with the environment variable
+// ISAM_FAIL_ALLOC=n (n >= 1) set when isam_plan starts, that call's n-th table or workspace
+// allocation fails as if the device were out of memory.  Read once per isam_plan call.
+thread_local int g_fail_alloc = 0;
+
 template <typename T>
 int dalloc(T** ptr, size_t n) {
+    if (g_fail_alloc > 0 && --g_fail_alloc == 0) {
+        *ptr = nullptr;
+        return ISAM_ENOMEM;
+    }
     if (hipMalloc((void**)ptr, n * sizeof(T)) != hipSuccess) {
         *ptr = nullptr;
         return ISAM_ENOMEM;
@@ -511,6 +520,8 @@ extern "C" int isam_plan(const isam_geometry* g, void* stream, isam_plan_t* out)
     if (!p) return ISAM_ENOMEM;
     derive(p, g);
     p->device = dev;
+    g_fail_alloc = 0;
+    if (const char* env = std::getenv("ISAM_FAIL_ALLOC")) g_fail_alloc = std::atoi(env);
     if (const char* env = std::getenv("ISAM_LAT_C")) p->lat_c = std::atoi(env);
     if (const char* env = std::getenv("ISAM_LAT_CR")) p->lat_cr = std::atoi(env);
     const size_t full = (size_t)p->ncol * p->nk, half = (size_t)p->nhalf * p->nk;

@@ -30,7 +30,7 @@ EXPORTS = (
     "isam_batch_plan", "isam_batch_offsets", "isam_batch_scan_plan", "isam_batch_set_calibration",
     "isam_batch_forward", "isam_batch_adjoint", "isam_batch_fista", "isam_batch_tune", "isam_batch_tiles",
     "isam_batch_set_tiles", "isam_batch_destroy", "isam_fista_ex", "isam_fista_state_bytes", "isam_direct",
-    "isam_direct_static",
+    "isam_direct_static", "isam_plan_stolt", "isam_plan_weights",
 )
 ISAM_BATCH_NO_GRAPH = 1
 
@@ -108,6 +108,8 @@ def load_library() -> ctypes.CDLL:
                                       ctypes.POINTER(dbl), vp, ctypes.POINTER(FistaInfo), vp]
         lib.isam_fista_state_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
         lib.isam_direct.argtypes = [vp, vp, vp, vp]
+        lib.isam_plan_stolt.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+        lib.isam_plan_weights.argtypes = [vp, vp, ctypes.c_int, vp, vp]
         lib.isam_direct_static.argtypes = [ctypes.POINTER(Geometry), vp, vp, vp]
         lib.isam_destroy.argtypes = [vp]
         lib.isam_destroy.restype = None
@@ -325,6 +327,23 @@ class Plan:
             import numpy as np
             h = np.ctypeslib.as_array(hist)[:3 * info.iters_run].reshape(info.iters_run, 3).copy()
         return FistaResult(out, info.iters_run, info.status, info.rel_res, info.resid2, info.l1, info.L, h)
+
+    def stolt_points(self, col: int, stream=None):
+        """(floor(t), tau) of every sample of column col, as the kernels compute them."""
+        fl = torch.empty(self.nk, dtype=torch.int32, device="cuda")
+        tau = torch.empty(self.nk, dtype=torch.float32, device="cuda")
+        _check(self._lib.isam_plan_stolt(self._h, int(col), fl.data_ptr(), tau.data_ptr(), _stream(stream)),
+               "isam_plan_stolt")
+        return fl, tau
+
+    def weights(self, tau: torch.Tensor, stream=None) -> torch.Tensor:
+        """The plan's min-max weight table evaluated at tau (device float32): complex64 [n][6]."""
+        _dev_tensor(tau, torch.float32, tuple(tau.shape), "tau")
+        n = tau.numel()
+        out = torch.empty((n, 6), dtype=torch.complex64, device=tau.device)
+        _check(self._lib.isam_plan_weights(self._h, tau.data_ptr(), n, out.data_ptr(), _stream(stream)),
+               "isam_plan_weights")
+        return out
 
     def direct(self, y: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
         """The direct IFFT image of Eq. 9 (dispersion-compensated per-A-scan transform)."""

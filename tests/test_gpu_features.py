@@ -158,3 +158,53 @@ def test_direct_image_of_a_volume_is_per_ascan(P):
         d = to_host(plan.direct(to_dev(y)))
     ref = O.direct_image(O.Geometry.of(o, nx=ny * nx), y.reshape(ny * nx, nk)).reshape(ny, nx, nk)
     assert rel(d, ref) < TOL_OP
+
+
+def test_plan_tables_against_oracle(P):
+    """The kernels' Stolt points (floor(t) exact, tau within FP32 rounding) and the plan's
+    piecewise-cubic min-max weight table (against the oracle's exact per-point least squares)
+    at the benchmark's depth length; focus at zero delay so the table holds the plain weights."""
+    import torch
+    o = ph.custom_optics(64, 2048, edge_phase2=40 * math.pi, edge_phase3=8 * math.pi, focus_rows=0)
+    g = O.Geometry.of(o)
+    t, g0, tau = O.stolt_points(g)
+    K = 2 * g.nk
+    rng = np.random.default_rng(47)
+    taus = np.concatenate([rng.uniform(0, 1, 2000), np.linspace(0, 1, 257)[:-1]]).astype(np.float32)
+    with P.Plan(P.Geometry.of(o)) as plan:
+        worst_tau, mism = 0.0, 0
+        for col in (0, 1, 17, 31, 32, 33, 63):
+            fl, tg = (to_host(x) for x in plan.stolt_points(col))
+            fl = fl.astype(np.int64)
+            fo = g0[col] + g.J // 2                              # oracle floor(t), reduced mod K
+            assert np.all(fl >= 0)
+            near = (tau[col] < 1e-6) | (tau[col] > 1 - 1e-6)
+            mism += int(np.count_nonzero((np.mod(fl, K) != fo) & ~near))
+            worst_tau = max(worst_tau, float(np.abs(tg - tau[col])[~near].max()))
+        w = to_host(plan.weights(torch.from_numpy(taus).cuda()))
+    assert mism == 0
+    assert worst_tau < 2e-7
+    ref = O.minmax_weights(g, taus.astype(np.float64))
+    err = np.abs(w - ref).max() / np.abs(ref).max()
+    print(f"Stolt tau max |diff| {worst_tau:.2e}; weight table max error {err:.2e} of max |u|")
+    assert err < 5e-7
+
+
+@pytest.mark.parametrize("nth", [1, 4, 12, 23])
+def test_plan_allocation_failure_is_clean(P, nth, monkeypatch):
+    """An allocation failing part-way through isam_plan (injected: the nth table or workspace
+    allocation) gives ISAM_ENOMEM, frees what was allocated, and leaves the library usable."""
+    import torch
+    o = ph.custom_optics(256, 1024)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    monkeypatch.setenv("ISAM_FAIL_ALLOC", str(nth))
+    with pytest.raises(P.IsamError) as ei:
+        P.Plan(P.Geometry.of(o))
+    assert ei.value.code == -4
+    monkeypatch.delenv("ISAM_FAIL_ALLOC")
+    torch.cuda.synchronize()
+    assert abs(torch.cuda.mem_get_info()[0] - free0) <= 4 << 20
+    with P.Plan(P.Geometry.of(o)) as plan:
+        s = plan.forward(torch.zeros((256, 1024), dtype=torch.complex64, device="cuda"))
+        assert float(s.abs().max()) == 0.0
