@@ -521,6 +521,9 @@ def main() -> int:
                              "peak": ALU_PEAK_TFS, "frac": round(achieved_tfs / ALU_PEAK_TFS, 4),
                              "peak_unpacked": ALU_PEAK_UNPACKED_TFS,
                              "frac_unpacked": round(achieved_tfs / ALU_PEAK_UNPACKED_TFS, 4)}}
+    if max(achieved_gbs / HBM_PEAK_GBS, achieved_tfs / ALU_PEAK_TFS) < 0.5:
+        roofline["limiter"] = ("neither roof: instruction issue with barrier and LDS latency inside a "
+                               "workgroup (one wave of workgroups fills the GPU at this size)")
     iter_bytes = sum(nbytes[k] for k in ("nufft_fwd", "nufft_adj", "fista_update"))
 
     progress("per-pass timings done")

@@ -207,3 +207,28 @@ def test_batched_fista_one_scan_per_depth_length_against_oracle(P):
         print(f"scan {i} ({scans[i][0]}x{scans[i][1]}): rel l2 {e:.2e}")
         assert infos[i].status == 0 and infos[i].iters_run == iters
         assert e < TOL_FISTA, i
+
+
+def test_largest_bscan_sampled(P):
+    """The largest B-scan the library builds: 2048 A-scans x 4096 samples (K = 8192 depth FFT,
+    the widest lateral length).  A generic phantom's spectra on sampled spectral rows, and the
+    adjoint of spectra whose lateral spectrum sits on a few frequencies (the oracle's cost is a
+    few columns), including the highest |q|."""
+    nx, nk = 2048, 4096
+    o = ph.custom_optics(nx, nk, edge_phase2=40 * math.pi, edge_phase3=8 * math.pi, focus_rows=nk // 4)
+    g = O.Geometry.of(o)
+    rng = np.random.default_rng(48)
+    eta = ph.layers(rng, nx, nk, 4) + ph.point_scatterers(rng, nx, nk, 3000)
+    rows = [0, 1, 1000, 2048, 3071, 4095]
+    spec = np.zeros((nx, nk), np.complex128)
+    ls = [0, 5, 700, 1023, 1024]
+    for l in ls:
+        spec[l] = ph.complex_gaussian(rng, nk)
+    full = spec + np.conj(np.roll(spec[::-1], 1, axis=0))
+    r = np.real(np.fft.ifft(full, axis=0, norm="ortho"))
+    cols = sorted(set(ls) | {(nx - l) % nx for l in ls})
+    with P.Plan(P.Geometry.of(o)) as plan:
+        s = to_host(plan.forward(to_dev(eta)))
+        a = to_host(plan.adjoint(to_dev(r)))
+    assert rel(s[:, rows], O.forward_nufft(g, eta, rows=rows)) < TOL_OP
+    assert rel(a, O.adjoint_nufft(g, r, columns=cols)) < TOL_OP
