@@ -24,7 +24,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E
 # FP32 vector peaks: the published figure (packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2 x 2
-# flops x 2.4 GHz), and the rate without packed-FP32 instructions, which this build never emits
+# flops x 2.4 GHz), and the rate without packed-FP32 instructions, which the kernels are compiled without
 ALU_PEAK_TFS = 157.3
 ALU_PEAK_UNPACKED_TFS = 78.6
 METRIC = "A^H·A op pairs/s + FISTA iter/s, 1024×2048 B-scan FP32 vs plain; %HBM peak"
