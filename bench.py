@@ -443,6 +443,24 @@ def main() -> int:
     progress(f"operator legs done: {1.0 / pair_s:.0f} pairs/s, {1.0 / normal_s:.0f} normal/s, "
              f"{1.0 / direct_s:.0f} direct images/s")
 
+    # ---- FISTA variants, ahead of the headline timing: iterations with the Eq. 15 norms
+    # formed every iteration (a tolerance that never holds; at least 200, so that the rate is
+    # not dominated by a call's fixed costs), and the paper's tol = 1e-3 solve (Sec.
+    # "Parameters") run to its stop.  Sustained solver work right before the headline run also
+    # brings the GPU's clocks to their level under load.  A two-iteration call first takes the
+    # process's one-time costs of the solver's first launches.
+    plan.fista(y, lam, 2, L=L, tol=1e-30, out=out)
+    n15 = max(args.steps, 200)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r15 = plan.fista(y, lam, n15, L=L, tol=1e-30, out=out)
+    torch.cuda.synchronize()
+    wall15 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    rtol = plan.fista(y, lam, 5000, L=L, tol=1e-3, out=out)
+    torch.cuda.synchronize()
+    wall_tol = time.perf_counter() - t0
+
     # ---- FISTA: warm-up, then exactly `steps` iterations in one timed region
     if args.warmup > 0:
         plan.fista(y, lam, args.warmup, L=L, out=out)
@@ -459,19 +477,8 @@ def main() -> int:
     if res.status != 0 or not math.isfinite(res.resid2):
         print(f"bench.py: FISTA status {res.status}", file=sys.stderr)
         return 1
-    # the same iterations with the Eq. 15 norms formed every iteration (a tolerance that never
-    # holds), and the paper's tol = 1e-3 solve (Sec. "Parameters") run to its stop
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    r15 = plan.fista(y, lam, args.steps, L=L, tol=1e-30, out=out)
-    torch.cuda.synchronize()
-    wall15 = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    rtol = plan.fista(y, lam, 5000, L=L, tol=1e-3, out=out)
-    torch.cuda.synchronize()
-    wall_tol = time.perf_counter() - t0
 
-    progress(f"FISTA {args.steps / wall:.0f} iter/s; with Eq. 15 norms {args.steps / wall15:.0f} iter/s; "
+    progress(f"FISTA {args.steps / wall:.0f} iter/s; with Eq. 15 norms {n15 / wall15:.0f} iter/s; "
              f"tol 1e-3 stop after {rtol.iters} iterations")
 
     # ---- per-pass kernel durations (HIP events on the launch stream) over a second FISTA run
@@ -566,7 +573,7 @@ def main() -> int:
         "ms_per_pair": round(1e3 * pair_s, 5),
         "normal_per_s": round(1.0 / normal_s, 2),
         "direct_images_per_s": round(1.0 / direct_s, 2),
-        "fista_eq15_norms_iter_per_s": round(args.steps / wall15, 2),
+        "fista_eq15_norms_iter_per_s": round(n15 / wall15, 2),
         "fista_tol_1e-3": {"iters": rtol.iters, "status": rtol.status, "rel_res": rtol.rel_res,
                            "seconds": round(wall_tol, 5), "iter_per_s": round(rtol.iters / wall_tol, 2)},
         "roofline": roofline,

@@ -377,7 +377,7 @@ __global__ __launch_bounds__((LatCfg<N, C>::T)) void k_lat_fista_batch(const Lat
 
 template <typename K>
 void set_lds(K kern, size_t bytes) {
-    if (bytes > 65536) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    set_max_lds((const void*)kern, bytes);
 }
 
 // sign -1: row-major object -> blocked lateral spectrum; sign +1: blocked -> row-major.

@@ -647,8 +647,7 @@ __global__ __launch_bounds__(2 * NuAdjCfg<K>::T, NuAdjCfg<K>::WPE) void k_nufft_
 
 template <typename Kern>
 void set_lds(Kern kern, size_t bytes) {
-    if (bytes > 65536)
-        (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    set_max_lds((const void*)kern, bytes);
 }
 
 template <int K>

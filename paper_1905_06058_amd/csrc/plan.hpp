@@ -18,10 +18,16 @@ extern thread_local PassEvents g_pass_events;
 
 }  // namespace isam
 
-// Launch of a pass kernel (hipLaunchKernelGGL plus the timing events of the pass, if any).
-#define ISAM_LAUNCH(KERNEL, GRID, BLOCK, LDS, S, ...)                                              \
-    hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, LDS, S, isam::g_pass_events.start, isam::g_pass_events.stop, \
-                          0u, __VA_ARGS__)
+// Launch of a pass kernel: with the timing events of the pass when isam_timing has set them,
+// else a plain launch.
+#define ISAM_LAUNCH(KERNEL, GRID, BLOCK, LDS, S, ...)                                                  \
+    do {                                                                                             \
+        if (isam::g_pass_events.start)                                                               \
+            hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, LDS, S, isam::g_pass_events.start,            \
+                                  isam::g_pass_events.stop, 0u, __VA_ARGS__);                        \
+        else                                                                                         \
+            hipLaunchKernelGGL(KERNEL, GRID, BLOCK, LDS, S, __VA_ARGS__);                            \
+    } while (0)
 
 namespace isam {
 
@@ -173,6 +179,9 @@ struct isam_plan_s {
     double* host_sums = nullptr;  // pinned host copy of red.sums
     isam::StopState* stop = nullptr;       // device stop-rule state of the solver
     isam::StopState* host_stop = nullptr;  // pinned host copy
+    // device addresses of the two pinned host records, which the solver's last kernel writes
+    double* host_sums_dev = nullptr;
+    isam::StopState* host_stop_dev = nullptr;
     double* hist = nullptr;       // per-iteration FISTA history [cap][3] (device), grown on demand
     int hist_cap = 0;
 
@@ -203,6 +212,9 @@ hipError_t lat_fista(const isam_plan_s* p, float2* eta_hat, const float2* ghat, 
 int lat_blocks(const isam_plan_s* p, int kind);   // number of workgroups of a lateral pass
 int lat_l(const isam_plan_s* p);                  // radix cap (log2) of the lateral FFT
 
+// Raise a kernel's dynamic LDS limit to bytes (needed above 64 KiB), once per kernel and device.
+void set_max_lds(const void* kern, size_t bytes);
+
 // Forward Stolt NUFFT: zh = Z (yhat null) or the residual spectrum Z - yhat; ||.||^2 partials
 // (Parseval weights) per workgroup into partials slot 0 if partials is non-null.
 hipError_t nufft_fwd(const isam_plan_s* p, const float2* etahat, const float2* yhat, float2* zh, float* partials,
@@ -220,10 +232,12 @@ hipError_t nufft_adj_batch(int K, const NuScan* recs, const int2* map, int nblk,
 int lat_tile(int nx, int sel, int real);        // lanes per tile built for (nx, sel)
 int lat_radix_cap(int nx, int sel, int real);   // radix cap (log2) of that configuration
 // FISTA set-up and output steps shared by the single and batched solvers (solver.hip).
-// zero_state: start from eta^1 = z^0 = 0 (false: the caller restores a saved state).  Also
+// zero_state: zero both state arrays, for a start from eta^1 = z^0 = 0 (false: the caller
+// restores a saved state, or has its first iteration clear them, see fista_first).  Also
 // resets the plan's device stop state.
 int fista_prepare(isam_plan_t p, const float* y, const float* w, hipStream_t s, bool zero_state = true);
-int fista_finish(isam_plan_t p, double L, int add_residual, float2* out, hipStream_t s);
+// convert: write z^k into out (false: the caller has done so).
+int fista_finish(isam_plan_t p, double L, int add_residual, float2* out, hipStream_t s, bool convert = true);
 // Whether a lateral length has built kernels (powers of two up to 2048 and 3, 5, 7 times
 // powers of two from 192 up to 1792).
 bool lat_supported(int nx);

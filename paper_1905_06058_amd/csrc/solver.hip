@@ -9,6 +9,7 @@
 //                is kept in lateral frequency, so an iteration is three passes.
 #include <algorithm>
 #include <cmath>
+#include <limits>
 #include <new>
 
 #include "common.hpp"
@@ -161,6 +162,65 @@ __global__ void k_from_blk_c(const float2* __restrict__ src, float2* __restrict_
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         const size_t j = i % m;
         dst[i] = src[i - j + blk((int)(j / cols), (int)(j % cols), rows)];
+    }
+}
+
+// First iteration of a fresh FISTA solve (Alg. 1 starts from eta^1 = z^0 = 0).  A eta^1 = 0,
+// so the forward pass's residual spectrum is -F(y): workgroup b writes it for the rows of
+// column pair b (the forward NUFFT's pairs), with that pass's ||r||^2 partial for the pair
+// (Parseval weights as there: a partner pair with one stored row counts it twice).  All
+// workgroups also clear the two state arrays (the momentum point and the iterate, 2 n4
+// complex values each), which the first adjoint and update pass read.
+__global__ __launch_bounds__(256) void k_fista_first(const isam::FwdPair* __restrict__ pairs, int nk, int nh,
+                                                     const float2* __restrict__ yhat, float2* __restrict__ rh,
+                                                     float* __restrict__ partials, float4* __restrict__ sa,
+                                                     float4* __restrict__ sb, size_t n4) {
+    __shared__ float red[4];
+    const isam::FwdPair pr = pairs[blockIdx.x];
+    float acc[1] = {0.f};
+    for (int i = threadIdx.x; i < nk; i += 256) {
+        const unsigned oa = blk(pr.ha, i, nh);
+        const float2 a = yhat[oa];
+        rh[oa] = c2(-a.x, -a.y);
+        if (pr.hb >= 0) {
+            const unsigned ob = blk(pr.hb, i, nh);
+            const float2 b = yhat[ob];
+            rh[ob] = c2(-b.x, -b.y);
+            acc[0] += cabs2(a) + cabs2(b);
+        } else {
+            acc[0] += (pr.mode == 0 ? 2.f : 1.f) * cabs2(a);
+        }
+    }
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n4; i += (size_t)gridDim.x * 256) {
+        sa[i] = z4;
+        sb[i] = z4;
+    }
+    block_sum_store<256, 1>(acc, red, partials + blockIdx.x * kRedSlots);
+}
+
+// End of a FISTA solve in one launch.  Workgroups [0, nconv): z^k from the blocked layout
+// into the row-major output.  Workgroup nconv: ||A eta^k - y||^2 from the forward pass's
+// partials (pa, na workgroups, slot 0) into hsums[0].  Workgroup nconv + 1: the update pass's
+// four sums (pb, nb workgroups, slots 0..3) into hsums[1..4], and the stop state into hstop
+// if non-null.  hsums and hstop are device addresses of pinned host records.
+__global__ __launch_bounds__(256) void k_fista_end(const float2* __restrict__ src, float2* __restrict__ dst,
+                                                   int rows, int cols, int slabs, int nconv,
+                                                   const float* __restrict__ pa, int na,
+                                                   const float* __restrict__ pb, int nb, double* hsums,
+                                                   const isam::StopState* __restrict__ st,
+                                                   isam::StopState* hstop) {
+    if ((int)blockIdx.x < nconv) {
+        const size_t m = (size_t)rows * cols, n = m * slabs;
+        for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)nconv * blockDim.x) {
+            const size_t j = i % m;
+            dst[i] = src[i - j + blk((int)(j / cols), (int)(j % cols), rows)];
+        }
+    } else if ((int)blockIdx.x == nconv) {
+        finalize_block(pa, na, 1, hsums, 0);
+    } else {
+        finalize_block(pb, nb, 4, hsums + 1, 0);
+        if (hstop && threadIdx.x == 0) *hstop = *st;
     }
 }
 
@@ -466,11 +526,13 @@ int fista_prepare(isam_plan_t p, const float* y, const float* w, hipStream_t s, 
 
 // FISTA output: z^k in row-major order, plus the optional residual step of Alg. 1,
 // z += (1/L) A^H (y - A z).
-int fista_finish(isam_plan_t p, double L, int add_residual, float2* out, hipStream_t s) {
+int fista_finish(isam_plan_t p, double L, int add_residual, float2* out, hipStream_t s, bool convert) {
     const size_t n = (size_t)p->ncol * p->nk;
     const int gb = grid_for(n);
-    hipLaunchKernelGGL(k_from_blk_c, dim3(gb), dim3(256), 0, s, p->zblk, out, p->nx, p->nk, p->ny);
-    HIP_OK(hipGetLastError());
+    if (convert) {
+        hipLaunchKernelGGL(k_from_blk_c, dim3(gb), dim3(256), 0, s, p->zblk, out, p->nx, p->nk, p->ny);
+        HIP_OK(hipGetLastError());
+    }
     if (add_residual) {
         int rc = normal_impl(p, out, p->yhat, p->vec, s);
         if (rc) return rc;
@@ -516,8 +578,13 @@ extern "C" int isam_fista_ex(isam_plan_t p, const float* y, float lambda, const 
         p->hist = h;
         p->hist_cap = max_iter;
     }
+    // A fresh solve starts from eta^1 = z^0 = 0 (Alg. 1).  Its first iteration replaces the
+    // forward pass of that zero input by k_fista_first, which also clears the state arrays,
+    // so they are cleared up front only when no iteration runs.
+    const bool fresh = resume == nullptr;
+    static_assert(sizeof(float4) == 2 * sizeof(float2), "state arrays cleared two values at a time");
     {
-        const int rc = isam::fista_prepare(p, y, w, s, resume == nullptr);
+        const int rc = isam::fista_prepare(p, y, w, s, fresh && max_iter == 0);
         if (rc) return rc;
     }
     // resume: the momentum point (lateral spectrum) and the last iterate, as saved
@@ -553,13 +620,21 @@ extern "C" int isam_fista_ex(isam_plan_t p, const float* y, float lambda, const 
     bool polled_stop = false;
     for (int it = 1; it <= max_iter; ++it) {
         const int k = kbase + it;
-        // the momentum point lives in the x spectrum; a volume's NUFFT needs the y transform too
-        const float2* eh = p->fista_hat;
-        if (vol) {
-            TIMED(7, lat_c2c_y(p, p->fista_hat, p->etahat, p->nx * p->nk, -1, s));
-            eh = p->etahat;
+        if (fresh && it == 1) {
+            // eta^1 = 0: the residual spectrum is -F(y), and the state arrays are cleared here
+            hipLaunchKernelGGL(k_fista_first, dim3(rb), dim3(256), 0, s, p->pairs, p->nk, p->nhalf, p->yhat,
+                               p->rh, part_r, reinterpret_cast<float4*>(p->fista_hat),
+                               reinterpret_cast<float4*>(p->zblk), n / 2);
+            HIP_OK(hipGetLastError());
+        } else {
+            // the momentum point lives in the x spectrum; a volume's NUFFT needs the y transform too
+            const float2* eh = p->fista_hat;
+            if (vol) {
+                TIMED(7, lat_c2c_y(p, p->fista_hat, p->etahat, p->nx * p->nk, -1, s));
+                eh = p->etahat;
+            }
+            TIMED(1, nufft_fwd(p, eh, p->yhat, p->rh, part_r, s, stop));
         }
-        TIMED(1, nufft_fwd(p, eh, p->yhat, p->rh, part_r, s, stop));
         TIMED(4, nufft_adj(p, p->rh, p->ghat, s, stop, fs.pre ? p->fista_hat : nullptr, fs.step));
         const float2* gx = p->ghat;
         if (vol) {
@@ -585,23 +660,32 @@ extern "C" int isam_fista_ex(isam_plan_t p, const float* y, float lambda, const 
         }
         t = t_next;
     }
-    // One synchronisation at the end: the stop state (if not just read), the final norms
-    // (||A eta^k - y||^2 from the last forward pass into sums[0], the update pass's four into
-    // sums[1..4]), the output, the saved state and the history are all enqueued first.
-    if (fs.norms && max_iter > 0 && !polled_stop)
-        HIP_OK(hipMemcpyAsync(p->host_stop, p->stop, sizeof(isam::StopState), hipMemcpyDeviceToHost, s));
+    // One synchronisation at the end: the output, the final norms (||A eta^k - y||^2 from the
+    // last forward pass, the update pass's four sums), the stop state, the saved state and the
+    // history are all enqueued first.  One kernel writes the output and the norms and stop
+    // state, the latter straight into the pinned host records.  Those are first set to NaN
+    // (and a zero stop state), so that a record the kernel did not write cannot pass for a
+    // result.
     if (max_iter > 0) {
-        hipLaunchKernelGGL(k_finalize2, dim3(2), dim3(256), 0, s, part_r, rb, 1, p->red.sums, part_f, fb, 4,
-                           p->red.sums + 1);
+        for (int i = 0; i < 5; ++i) p->host_sums[i] = std::numeric_limits<double>::quiet_NaN();
+        if (fs.norms && !polled_stop) {
+            p->host_stop->iter = 0;
+            p->host_stop->status = ISAM_ENONFINITE;
+            p->host_stop->rel_res = std::numeric_limits<double>::quiet_NaN();
+        }
+        const int cb = grid_for(n);
+        hipLaunchKernelGGL(k_fista_end, dim3(cb + 2), dim3(256), 0, s, p->zblk, (float2*)eta_out, p->nx, p->nk,
+                           p->ny, cb, part_r, rb, part_f, fb, p->host_sums_dev, p->stop,
+                           fs.norms && !polled_stop ? p->host_stop_dev : nullptr);
         HIP_OK(hipGetLastError());
-        HIP_OK(hipMemcpyAsync(p->host_sums, p->red.sums, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
     }
     if (save) {
         HIP_OK(hipMemcpyAsync(save->data, p->fista_hat, n * sizeof(float2), hipMemcpyDeviceToDevice, s));
         HIP_OK(hipMemcpyAsync((float2*)save->data + n, p->zblk, n * sizeof(float2), hipMemcpyDeviceToDevice, s));
     }
     {
-        const int rc = isam::fista_finish(p, L, add_residual, (float2*)eta_out, s);
+        // the output conversion is done above when iterations ran
+        const int rc = isam::fista_finish(p, L, add_residual, (float2*)eta_out, s, max_iter == 0);
         if (rc) return rc;
     }
     HIP_OK(hipStreamSynchronize(s));

@@ -10,7 +10,9 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "common.hpp"
@@ -445,6 +447,29 @@ int dalloc(T** ptr, size_t n) {
     return ISAM_OK;
 }
 
+}  // namespace
+
+namespace isam {
+
+void set_max_lds(const void* kern, size_t bytes) {
+    if (bytes <= 65536) return;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    // kernels (and devices) whose limit is already raised: the attribute call then costs
+    // nothing on the launch path
+    static std::mutex mu;
+    static std::vector<std::pair<const void*, int>> done;
+    std::lock_guard<std::mutex> lock(mu);
+    for (const auto& d : done)
+        if (d.first == kern && d.second == dev) return;
+    if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess)
+        done.emplace_back(kern, dev);
+}
+
+}  // namespace isam
+
+namespace {
+
 void release(isam_plan_s* p) {
     void* ptrs[] = {p->q2, p->Bl, p->En, p->sm, p->wtab, p->twK, p->twK8, p->twX[2], p->twX[3], p->twX[4],
                     p->twY[2], p->twY[3], p->twY[4], p->pairs, p->wscratch, p->twN, p->Dn, p->Pm, p->hist,
@@ -565,11 +590,17 @@ extern "C" int isam_plan(const isam_geometry* g, void* stream, isam_plan_t* out)
     rc = rc ? rc : dalloc(&p->zblk, full);
     rc = rc ? rc : dalloc(&p->red.partials, (size_t)p->red.maxBlocks * kRedSlots);
     rc = rc ? rc : dalloc(&p->red.sums, kRedSlots);
-    if (rc == ISAM_OK && hipHostMalloc((void**)&p->host_sums, kRedSlots * sizeof(double)) != hipSuccess)
+    // The two host records are mapped and coherent, so that a kernel can write them directly
+    // (visible to the host once the stream has been synchronised).
+    constexpr unsigned kHostFlags = hipHostMallocMapped | hipHostMallocCoherent;
+    if (rc == ISAM_OK && hipHostMalloc((void**)&p->host_sums, kRedSlots * sizeof(double), kHostFlags) != hipSuccess)
         rc = ISAM_ENOMEM;
     if (rc == ISAM_OK && hipMalloc((void**)&p->stop, sizeof(isam::StopState)) != hipSuccess) rc = ISAM_ENOMEM;
-    if (rc == ISAM_OK && hipHostMalloc((void**)&p->host_stop, sizeof(isam::StopState)) != hipSuccess)
+    if (rc == ISAM_OK && hipHostMalloc((void**)&p->host_stop, sizeof(isam::StopState), kHostFlags) != hipSuccess)
         rc = ISAM_ENOMEM;
+    if (rc == ISAM_OK && (hipHostGetDevicePointer((void**)&p->host_sums_dev, p->host_sums, 0) != hipSuccess ||
+                          hipHostGetDevicePointer((void**)&p->host_stop_dev, p->host_stop, 0) != hipSuccess))
+        rc = ISAM_EHIP;
     hipStream_t s = (hipStream_t)stream;
     if (rc == ISAM_OK) rc = build_twiddles(p, s);
     if (rc == ISAM_OK) rc = build_calibrated_tables(p, s);

@@ -74,6 +74,50 @@ def test_fista_resume_is_bitwise_and_matches_oracle(P):
     assert abs(st.t - t) < 1e-12 * t
 
 
+def test_fista_first_iteration_and_end_records(P):
+    """A fresh solve starts from eta^1 = z^0 = 0 (Alg. 1): its first iteration takes the residual
+    as -y without a forward transform and clears the state itself.  The norms of the solve's
+    last iteration and the stop state reach the host through the pinned records the final
+    kernel writes; consecutive solves with other data, weights and tolerances each report
+    their own.  A fresh zero-iteration call returns the zero image."""
+    import torch
+    w, g, op, y = tiny_problem()
+    yd = to_dev(y)
+    wts = ph.depth_weights(g.nx, g.nk)
+    y2 = 0.5 * y[::-1].copy()
+    with P.Plan(P.Geometry.of(w.optics)) as plan:
+        L = plan.lipschitz(iters=50, seed=0)
+        lam = 0.05 * plan.lambda_max(yd)
+        one = plan.fista(yd, lam, 1, L=L, history=True)
+        ref1 = O.fista(op, y, lam, L, 1)
+        assert one.iters == 1 and one.status == 0
+        assert rel(to_host(one.eta), ref1.z) < TOL_FISTA
+        yy = float(np.sum(y * y))
+        assert abs(one.resid2 - yy) <= 1e-5 * yy            # ||A eta^1 - y||^2 = ||y||^2
+        assert abs(one.history[0, 1] - ref1.resid2[0]) <= 1e-5 * ref1.resid2[0]
+        assert abs(one.l1 - ref1.l1[0]) <= 1e-4 * ref1.l1[0]
+        cases = ((y, 0.05, 20, None, 0.0), (y2, 0.2, 7, wts, 0.0), (y, 0.05, 200, None, 1e-2),
+                 (y2, 0.1, 33, wts, 0.0))
+        for yc, frac, iters, wc, tol in cases:
+            ycd = to_dev(yc)
+            wd = None if wc is None else to_dev(wc)
+            lam_c = frac * plan.lambda_max(ycd, wd)
+            res = plan.fista(ycd, lam_c, iters, L=L, w=wd, tol=tol)
+            assert res.status == 0
+            ref = O.fista(op, yc, lam_c, L, res.iters, w=wc)
+            assert rel(to_host(res.eta), ref.z) < TOL_FISTA
+            assert abs(res.resid2 - ref.resid2[-1]) <= 1e-4 * ref.resid2[-1]
+            assert abs(res.l1 - ref.l1[-1]) <= 1e-4 * ref.l1[-1]
+            if tol > 0:
+                assert res.iters < iters and res.rel_res < tol
+                assert abs(res.rel_res - ref.rel_res[-1]) <= 1e-3 * ref.rel_res[-1] + 1e-6
+            else:
+                assert res.iters == iters and res.rel_res == -1.0
+        zero = plan.fista(yd, lam, 0, L=L)
+        assert zero.iters == 0 and zero.status == 0
+        assert torch.count_nonzero(zero.eta).item() == 0
+
+
 def test_fista_history_matches_oracle(P):
     w, g, op, y = tiny_problem()
     wts = ph.depth_weights(g.nx, g.nk)
