@@ -397,7 +397,11 @@ extern "C" int isam_batch_plan(const isam_geometry* geoms, int nscans, void* str
         return rc;
     }
     for (int i = 0; i < nscans; ++i) {
-        const isam_plan_s* p = b->plans[i];
+        isam_plan_s* p = b->plans[i];
+        // the batch chooses the lateral tile widths per group (default, tuned or set); the
+        // scans' own plans follow them, so that a scan and the batch compute alike
+        p->lat_c = 0;
+        p->lat_cr = 0;
         auto find = [](std::vector<Group>& gs, int key) -> Group& {
             for (Group& g : gs)
                 if (g.key == key) return g;

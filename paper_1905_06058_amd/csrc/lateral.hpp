@@ -498,7 +498,10 @@ hipError_t launch_fista_batch(int norms, const LatScan* recs, const int2* map, i
     }
 #define ISAM_LAT_SWITCH(CALL) ISAM_LAT_DISPATCH(p->nx, p->lat_c, ISAM_LAT_DEF_C, CALL)
 #define ISAM_LAT_SWITCH_R(CALL) ISAM_LAT_DISPATCH(p->nx, p->lat_cr, ISAM_LAT_DEF_CR, CALL)
-#define ISAM_LAT_DEF_C (N >= 2048 ? 4 : 8)
+// Default complex tile width: 8 lanes, but 4 above 1280 points, where an 8-lane tile of the
+// update pass spills registers (1536 and 1792 points: 41.9 and 36.3 us against 18.3 and 19.0
+// with 4 lanes, at 1024 depth columns) and 2048 points build no 8-lane tile.
+#define ISAM_LAT_DEF_C (N > 1280 ? 4 : 8)
 #define ISAM_LAT_DEF_CR 4
 // Built lateral lengths: powers of two (up to 128 with fixed 8-lane tiles, above with a
 // tunable width) and 3, 5, 7 times powers of two from 192 to 1792.

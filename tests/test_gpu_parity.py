@@ -356,12 +356,13 @@ def test_fista_mixed_radix_lateral_length(P):
 
 
 @pytest.mark.parametrize("nx", [768, 1024])
-def test_fista_wide_lateral_tiles(P, nx):
+def test_fista_wide_lateral_tiles(P, nx, monkeypatch):
     """Lateral tiles of 8 lanes x nx >= 4096 points run the update pass with two LDS buffers:
     nx = 1024 has an odd pass count (chained transforms skip the opening barrier), nx = 768
     (3 x 256) an even one with more butterflies than threads in its outer passes.  40 FISTA
     iterations (the device stop check, with its extra transform, runs every 16) against the
-    oracle."""
+    oracle.  The 8-lane tiles are requested explicitly (a plan this shallow would take 4)."""
+    monkeypatch.setenv("ISAM_LAT_C", "8")
     nk = 64
     o = ph.custom_optics(nx, nk, edge_phase2=12 * math.pi, edge_phase3=2 * math.pi, focus_rows=9)
     g = O.Geometry.of(o)
