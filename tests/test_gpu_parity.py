@@ -338,6 +338,30 @@ def test_fista_at_full_depth_length(P):
     assert abs(res.resid2 - ref.resid2[-1]) < 1e-4 * ref.resid2[-1]
 
 
+@pytest.mark.parametrize("nx,nk", [(1536, 32), (1280, 64), (1024, 128)])
+def test_fista_four_lane_tiles(P, nx, nk):
+    """Plans that take 4-lane lateral tiles by default (above 1280 points; at 1024 and 1280
+    points with fewer than 2048 depth columns): 30 FISTA iterations with the Eq. 15 stop check
+    (tolerance never met) against the oracle, the update pass in its forms with and without
+    the norms."""
+    o = ph.custom_optics(nx, nk, edge_phase2=12 * math.pi, edge_phase3=2 * math.pi, focus_rows=nk // 8)
+    g = O.Geometry.of(o)
+    rng = np.random.default_rng(nx + nk)
+    eta = ph.layers(rng, nx, nk, 2) + ph.point_scatterers(rng, nx, nk, nx // 16)
+    op = O.Operator(g, "N")
+    y = ph.add_noise(op.A(eta), 25.0, nx)
+    with make_plan(P, o) as plan:
+        L = plan.lipschitz(iters=50, seed=0)
+        lam = 0.05 * plan.lambda_max(to_dev(y))
+        plain = plan.fista(to_dev(y), lam, 30, L=L)
+        normed = plan.fista(to_dev(y), lam, 30, L=L, tol=1e-12)
+    ref = O.fista(op, y, lam, L, 30)
+    assert normed.iters == 30
+    for res in (plain, normed):
+        assert rel(to_host(res.eta), ref.z) < TOL_FISTA
+        assert abs(res.resid2 - ref.resid2[-1]) < 1e-4 * ref.resid2[-1]
+
+
 def test_fista_mixed_radix_lateral_length(P):
     """384 A-scans (3 x 128): the FISTA pass runs a radix-3 lateral transform."""
     o = ph.custom_optics(384, 128, edge_phase2=20 * math.pi, edge_phase3=4 * math.pi, focus_rows=32)
