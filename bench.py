@@ -239,9 +239,10 @@ def accuracy_leg(P, torch, w, op, y) -> dict:
 def batch_leg(P, torch, iters: int, nscans: int = 64, nx_choices=tuple(range(256, 1025, 128)),
               nk_choices=(1024, 2048), label: str = "") -> dict:
     """B-scans of uneven size (by default 64 of them, nx from {256, 384, ..., 1024}, nk from
-    {1024, 2048}), own phantom and dispersion each: one batch (tuned tiles, captured iteration
-    graph) against the same scans run one after another through their own plans (one launch per
-    pass per scan)."""
+    {1024, 2048}), own phantom and dispersion each: one batch (tuned tiles and FISTA schedule)
+    against the same scans run one after another through their own plans (one launch per pass
+    per scan, one stream).  Both FISTA schedules are timed: grouped launches (captured iteration
+    graph, and eager) and each scan's own solve spread over the batch's streams."""
     import numpy as np
     import phantoms as ph
     rng = np.random.default_rng(3)
@@ -275,8 +276,17 @@ def batch_leg(P, torch, iters: int, nscans: int = 64, nx_choices=tuple(range(256
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / reps
 
-    t_batch = timed(lambda: b.fista(y, lam, iters, L=L, out=out), 3)
-    t_eager = timed(lambda: b.fista(y, lam, iters, L=L, out=out, graph=False), 3)
+    tuned = b.schedule()
+
+    def fista_time(sched, graph=True):
+        b.set_schedule(sched)
+        return timed(lambda: b.fista(y, lam, iters, L=L, out=out, graph=graph), 3)
+
+    t_grouped = fista_time("grouped")
+    t_eager = fista_time("grouped", graph=False)
+    t_streams = fista_time("streams")
+    b.set_schedule(tuned)
+    t_batch = t_grouped if tuned == "grouped" else t_streams
     t_scan = timed(lambda: [p.fista(ys[i], lam[i], iters, L=L[i], out=outs[i]) for i, p in enumerate(plans)], 3)
     x = torch.randn(b.total, dtype=torch.complex64, device="cuda")
     sb = torch.empty(b.total, dtype=torch.float32, device="cuda")
@@ -303,8 +313,11 @@ def batch_leg(P, torch, iters: int, nscans: int = 64, nx_choices=tuple(range(256
                               "own phantom, dispersion and focus each; synthetic"),
         "scans": nscans, "points": pts, "fista_iters": iters,
         "tiles": {str(k): v for k, v in tiles.items()},
+        "schedule": tuned,
         "batched_fista_iter_per_s": round(iters / t_batch, 2),
+        "grouped_fista_iter_per_s": round(iters / t_grouped, 2),
         "batched_eager_fista_iter_per_s": round(iters / t_eager, 2),
+        "streams_fista_iter_per_s": round(iters / t_streams, 2),
         "per_scan_fista_iter_per_s": round(iters / t_scan, 2),
         "fista_speedup": round(t_scan / t_batch, 3),
         "batched_pairs_per_s": round(1.0 / tp_batch, 2),

@@ -264,7 +264,9 @@ int isam_timing(isam_plan_t p, int enable, double* ms_out, int64_t* count_out);
  * adjoint (Eq. 17) and the FISTA iteration (Alg. 1) as one launch per group of
  * scans sharing a kernel specialisation (same nx for the lateral passes, same
  * nk for the NUFFT passes) instead of one launch per scan.  One FISTA
- * iteration is captured once in a hipGraph and replayed.
+ * iteration is captured once in a hipGraph and replayed.  FISTA has a second
+ * schedule, which runs each scan's own solve with the scans spread over the
+ * batch's streams; the tuner picks one of the two.
  *
  * Packed buffers: scan i occupies elements [off[i], off[i+1]) of every packed
  * buffer (isam_batch_offsets), row-major [nx_i][nk_i] as for a single plan;
@@ -274,8 +276,20 @@ int isam_timing(isam_plan_t p, int enable, double* ms_out, int64_t* count_out);
 typedef struct isam_batch_s* isam_batch_t;
 
 /* Flag of isam_batch_fista: launch the iteration's kernels one by one instead of
- * replaying the captured graph (same results, bit for bit). */
+ * replaying the captured graph (same results, bit for bit; grouped schedule only). */
 #define ISAM_BATCH_NO_GRAPH 1
+
+/* FISTA schedules of a batch (isam_batch_set_schedule, isam_batch_tune):
+ * GROUPED  one launch per pass per group of scans, the iteration replayed as a
+ *          graph; every scan advances one iteration per replay (the default);
+ * STREAMS  each scan's own solve (isam_fista on its plan) on one of four
+ *          streams of the batch (each with a hardware queue of its own), scans
+ *          dealt to streams by decreasing size, one host thread per stream
+ *          enqueueing its scans' solves in turn, so that passes of different
+ *          scans overlap.  Each scan's result is isam_fista's on its plan, bit for
+ *          bit; the calling thread's device is used. */
+#define ISAM_BATCH_SCHED_GROUPED 0
+#define ISAM_BATCH_SCHED_STREAMS 1
 
 /* Build a batch of nscans plans from geoms[0..nscans).  Errors: those of
  * isam_plan for any scan (the batch is then not created), EINVAL, ENOMEM. */
@@ -305,17 +319,27 @@ int isam_batch_adjoint(isam_batch_t b, const float* r, void* eta_out, void* stre
  * Eq. 15 per scan on the device (a scan that has stopped keeps its iterate;
  * the loop ends when all have stopped or after max_iter iterations); info:
  * host isam_fista_info[nscans] or NULL; flags: 0 or ISAM_BATCH_NO_GRAPH.
- * Synchronises the stream.  Returns the first non-OK scan status, if any. */
+ * Runs in the batch's schedule (ISAM_BATCH_SCHED_*).  Synchronises the stream.
+ * Returns the first non-OK scan status, if any. */
 int isam_batch_fista(isam_batch_t b, const float* y, const float* lambda, const float* w,
                      int max_iter, float tol, const double* L, int add_residual, int flags,
                      void* eta_out, isam_fista_info* info, void* stream);
 
 /* Autotuner: for every group of scans with nx >= 192, times the batched update
  * pass (complex tiles) and R2C pass (real tiles) at tile widths 2, 4 and 8
- * lanes, `reps` launches each, and keeps the fastest.  Waits for earlier work on
- * `stream`, clobbers the scans' solver workspaces (not their tables) and
- * synchronises. */
+ * lanes, `reps` launches each, and keeps the fastest; then times an 8-iteration
+ * FISTA call on zero data in each schedule (one warm-up call, then `reps` calls,
+ * host clock) and keeps the faster schedule.  Waits for earlier work on
+ * `stream`, clobbers the scans' solver workspaces (not their tables), allocates
+ * and frees two packed scratch buffers, and synchronises. */
 int isam_batch_tune(isam_batch_t b, int reps, void* stream);
+
+/* Set the FISTA schedule (ISAM_BATCH_SCHED_GROUPED or _STREAMS), e.g. from a
+ * saved tuning; EINVAL for any other value. */
+int isam_batch_set_schedule(isam_batch_t b, int sched);
+
+/* The FISTA schedule in use. */
+int isam_batch_schedule(isam_batch_t b, int* sched);
 
 /* Tile widths in use: for up to cap lateral groups, nx and the lanes per tile of
  * the complex and real passes; *ngroups receives the number of groups. */

@@ -30,9 +30,11 @@ EXPORTS = (
     "isam_batch_plan", "isam_batch_offsets", "isam_batch_scan_plan", "isam_batch_set_calibration",
     "isam_batch_forward", "isam_batch_adjoint", "isam_batch_fista", "isam_batch_tune", "isam_batch_tiles",
     "isam_batch_set_tiles", "isam_batch_destroy", "isam_fista_ex", "isam_fista_state_bytes", "isam_direct",
-    "isam_direct_static", "isam_plan_stolt", "isam_plan_weights",
+    "isam_direct_static", "isam_plan_stolt", "isam_plan_weights", "isam_batch_set_schedule",
+    "isam_batch_schedule",
 )
 ISAM_BATCH_NO_GRAPH = 1
+SCHEDULES = ("grouped", "streams")      # ISAM_BATCH_SCHED_GROUPED, ISAM_BATCH_SCHED_STREAMS
 
 PASS_NAMES = ("lateral_fft_fwd", "nufft_fwd", "lateral_c2r", "lateral_r2c", "nufft_adj",
               "lateral_fft_inv", "fista_update", "lateral_y", "direct")
@@ -131,6 +133,8 @@ def load_library() -> ctypes.CDLL:
         lib.isam_batch_tune.argtypes = [vp, ctypes.c_int, vp]
         lib.isam_batch_tiles.argtypes = [vp, i32p, i32p, i32p, i32, i32p]
         lib.isam_batch_set_tiles.argtypes = [vp, i32, i32, i32]
+        lib.isam_batch_set_schedule.argtypes = [vp, ctypes.c_int]
+        lib.isam_batch_schedule.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
         lib.isam_batch_destroy.argtypes = [vp]
         lib.isam_batch_destroy.restype = None
         for name in EXPORTS:
@@ -483,6 +487,18 @@ class Batch:
         nx, c, r = (ctypes.c_int32 * cap)(), (ctypes.c_int32 * cap)(), (ctypes.c_int32 * cap)()
         _check(self._lib.isam_batch_tiles(self._h, nx, c, r, cap, ctypes.byref(ng)), "isam_batch_tiles")
         return {int(nx[i]): (int(c[i]), int(r[i])) for i in range(min(ng.value, cap))}
+
+    def schedule(self) -> str:
+        """FISTA schedule in use: "grouped" (one launch per pass per group of scans, replayed
+        graph) or "streams" (each scan's own solve, scans spread over the batch's streams)."""
+        v = ctypes.c_int()
+        _check(self._lib.isam_batch_schedule(self._h, ctypes.byref(v)), "isam_batch_schedule")
+        return SCHEDULES[v.value]
+
+    def set_schedule(self, name: str) -> None:
+        if name not in SCHEDULES:
+            raise ValueError(f"schedule must be one of {SCHEDULES}")
+        _check(self._lib.isam_batch_set_schedule(self._h, SCHEDULES.index(name)), "isam_batch_set_schedule")
 
     def set_tiles(self, nx: int, lanes_complex: int, lanes_real: int) -> None:
         _check(self._lib.isam_batch_set_tiles(self._h, int(nx), int(lanes_complex), int(lanes_real)),

@@ -138,12 +138,55 @@ def test_batch_fista_stop_rule_per_scan(P):
             assert rel(to_host(b.scan(got, i)), to_host(ref.eta)) < 1e-6, i
 
 
+def test_batch_fista_streams_schedule_is_each_scans_own_solve(P):
+    """The streams schedule runs each scan's own solve (isam_fista's launches) on the batch's
+    streams: every scan's image and info equal its plan's isam_fista bit for bit, plain, with
+    the Eq. 15 stop, with weights and with the residual add-back; the grouped schedule agrees
+    within rounding."""
+    import torch
+    opts = optics_list()
+    with P.Batch([P.Geometry.of(o) for o in opts]) as b:
+        y, L, lam = _problem(P, b, opts, 11)
+        assert b.schedule() == "grouped"
+        b.set_schedule("streams")
+        assert b.schedule() == "streams"
+        rng = np.random.default_rng(5)
+        wts = packed(b, [rng.uniform(0.5, 1.0, (o.nx, o.nk)) for o in opts], torch.float32)
+        for kw in (dict(), dict(tol=3e-3), dict(w=wts), dict(add_residual=True)):
+            iters = 300 if "tol" in kw else 40
+            got, info = b.fista(y, lam, iters, L=L, **kw)
+            got = got.clone()
+            for i in range(b.n):
+                one = dict(kw)
+                if "w" in one:
+                    one["w"] = b.scan(wts, i).contiguous()
+                ref = b.plan(i).fista(b.scan(y, i).contiguous(), lam[i], iters, L=L[i], **one)
+                assert bool((b.scan(got, i) == ref.eta).all()), (sorted(kw), i)
+                assert info[i].iters_run == ref.iters, (sorted(kw), i)
+                assert info[i].status == ref.status == 0
+                assert info[i].resid2 == ref.resid2 and info[i].l1 == ref.l1
+                assert info[i].rel_res == ref.rel_res
+            if "tol" in kw:                                   # scans stop at different iterations
+                assert min(x.iters_run for x in info) < max(x.iters_run for x in info)
+        streams, _ = b.fista(y, lam, 40, L=L)
+        streams = streams.clone()
+        b.set_schedule("grouped")
+        grouped, _ = b.fista(y, lam, 40, L=L)
+        for i in range(b.n):
+            assert rel(to_host(b.scan(grouped, i)), to_host(b.scan(streams, i))) < 1e-6, i
+        with pytest.raises(ValueError):
+            b.set_schedule("persistent")
+        assert b._lib.isam_batch_set_schedule(b._h, 7) == -1     # ISAM_EINVAL
+        assert b.schedule() == "grouped"
+
+
 def test_batch_tuner_keeps_results_consistent(P):
     import torch
     opts = optics_list()
     etas, _ = batch_data(opts, 3)
     with P.Batch([P.Geometry.of(o) for o in opts]) as b:
         tiles = b.tune(reps=3)
+        assert b.schedule() in P.isam.SCHEDULES
         assert set(tiles) == {64, 192, 256, 384}
         for nx, (c, cr) in tiles.items():
             assert c in (2, 4, 8) and cr in (2, 4, 8)
@@ -199,3 +242,12 @@ def test_uneven_batch_of_sixty_four_scans(P):
         lhs = float((s.double() ** 2).sum())
         rhs = float((eta.conj() * a).real.double().sum())
         assert abs(lhs - rhs) <= 1e-5 * lhs
+        # FISTA in the streams schedule: each scan's own solve, bit for bit
+        L = [b.plan(i).lipschitz(iters=5, seed=0) for i in range(b.n)]
+        lam = [0.05 * b.plan(i).lambda_max(b.scan(s, i).contiguous()) for i in range(b.n)]
+        b.set_schedule("streams")
+        z, info = b.fista(s, lam, 12, L=L)
+        for i in range(0, 64, 9):
+            ref = b.plan(i).fista(b.scan(s, i).contiguous(), lam[i], 12, L=L[i])
+            assert bool((b.scan(z, i) == ref.eta).all()), i
+            assert info[i].resid2 == ref.resid2 and info[i].status == 0, i
