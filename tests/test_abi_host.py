@@ -103,6 +103,9 @@ def test_entry_points_reject_null_plan(lib):
     assert lib.isam_batch_adjoint(None, buf, buf, None) == -1
     assert lib.isam_batch_tune(None, 1, None) == -1
     assert lib.isam_batch_set_tiles(None, 256, 4, 4) == -1
+    assert lib.isam_batch_set_schedule(None, 0) == -1
+    sched = ctypes.c_int()
+    assert lib.isam_batch_schedule(None, ctypes.byref(sched)) == -1
     assert lib.isam_batch_offsets(None, None) == -1
     lib.isam_batch_destroy(None)
 
