@@ -430,8 +430,8 @@ int ensure_streams(isam_batch_t b) {
 // FISTA in the streams schedule: each scan's own solve (isam_fista_ex, so its result is that
 // of isam_fista on the scan's plan, bit for bit) on one of the batch's streams, scans dealt to
 // streams by decreasing size.  One host thread per stream enqueues its scans' solves one after
-// another (a single host thread interleaving all scans' launches kept the GPU less busy).  The
-// streams first wait for the caller's earlier work; every stream is complete on return.
+// another, each solve's host synchronisation holding up only its own stream.  The streams
+// first wait for the caller's earlier work; every stream is complete on return.
 int fista_streams(isam_batch_t b, const float* y, const float* lambda, const float* w, int max_iter, float tol,
                   const std::vector<double>& Ls, int add_residual, float2* out, isam_fista_info* info,
                   hipStream_t s) {
