@@ -180,6 +180,28 @@ def test_batch_fista_streams_schedule_is_each_scans_own_solve(P):
         assert b.schedule() == "grouped"
 
 
+def test_batch_fista_reports_a_non_finite_scan_in_both_schedules(P):
+    """NaN in one scan's spectra: the batched solve reports ISAM_ENONFINITE in either schedule,
+    and a clean batch afterwards solves as before (no state left behind)."""
+    import torch
+    opts = optics_list()
+    with P.Batch([P.Geometry.of(o) for o in opts]) as b:
+        y, L, lam = _problem(P, b, opts, 13)
+        ref, _ = b.fista(y, lam, 10, L=L)
+        ref = ref.clone()
+        bad = y.clone()
+        b.scan(bad, 2)[3, 5] = float("nan")
+        for sched in ("grouped", "streams"):
+            b.set_schedule(sched)
+            with pytest.raises(P.IsamError) as e:
+                b.fista(bad, lam, 10, L=L)
+            assert e.value.code == -7, sched                     # ISAM_ENONFINITE
+            got, info = b.fista(y, lam, 10, L=L)
+            for i in range(b.n):
+                assert rel(to_host(b.scan(got, i)), to_host(b.scan(ref, i))) < 1e-6, (sched, i)
+                assert info[i].status == 0
+
+
 def test_batch_tuner_keeps_results_consistent(P):
     import torch
     opts = optics_list()
