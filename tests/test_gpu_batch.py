@@ -202,6 +202,30 @@ def test_batch_fista_reports_a_non_finite_scan_in_both_schedules(P):
                 assert info[i].status == 0
 
 
+def test_batch_streams_schedule_orders_after_the_callers_stream(P):
+    """The streams schedule's streams wait for the caller's earlier work: spectra written on the
+    caller's stream behind a long-running kernel, with no synchronisation, give the same
+    images as spectra that were already in place."""
+    import torch
+    opts = optics_list()
+    with P.Batch([P.Geometry.of(o) for o in opts]) as b:
+        y, L, lam = _problem(P, b, opts, 17)
+        b.set_schedule("streams")
+        ref, _ = b.fista(y, lam, 15, L=L)
+        ref = ref.clone()
+        s = torch.cuda.Stream()
+        a = torch.randn(4096, 4096, device="cuda")
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            y2 = torch.zeros_like(y)
+            for _ in range(8):
+                a = a @ a * 1e-3                       # keeps the caller's stream busy for a while
+            y2.copy_(y)
+            got, _ = b.fista(y2, lam, 15, L=L, stream=s)
+        torch.cuda.synchronize()
+        assert bool((got == ref).all())
+
+
 def test_batch_tuner_keeps_results_consistent(P):
     import torch
     opts = optics_list()
